@@ -23,8 +23,10 @@
  *   R5  the perturbation operator carries the square (c_i . grad phi)^2 / |grad phi|^2,
  *       without which it does not conserve mass.
  *   R6  A is a run constant, A_r = A_b = A.
- *   R7  cos(theta_1) = 0 for the rest velocity; if |grad phi| = 0 both the perturbation
- *       and the recolouring segregation term vanish.
+ *   R7  cos(theta_1) = 0 for the rest velocity.  Where |grad phi| < 1e-5 the direction of
+ *       grad phi is not defined by the fields (at a symmetry point it is set by rounding
+ *       alone) and the recolouring term beta rho_r rho_b / rho^2 cos(theta_i) does not vanish
+ *       with |grad phi|; there both that term and the perturbation are taken as zero.
  *   R8  no-slip walls are half-way bounce-back, per colour; walls lie half a cell outside
  *       the first/last plane.  Gradient stencils see a ghost layer equal to the adjacent
  *       cell (zero normal gradient).
@@ -48,6 +50,7 @@
 #include <string.h>
 
 #define Q 27
+#define GRAD_PHI_MIN 1e-5 /* R7: |grad phi| below this defines no interface normal */
 
 enum { FACE_PERIODIC = 0, FACE_BOUNCEBACK = 1, FACE_FREESLIP = 2, FACE_OUTFLOW = 3 };
 
@@ -281,7 +284,7 @@ static void mrt_collide(const double M[Q][Q], const double Minv[Q][Q], const dou
  * the square of R5:  f_i += A |grad phi| [ w_i (c_i . grad phi)^2 / |grad phi|^2 - B_i ]. */
 void oracle_perturbation(double A, const double *gphi, double *f) {
   const double g2 = gphi[0] * gphi[0] + gphi[1] * gphi[1] + gphi[2] * gphi[2];
-  if (g2 == 0.0) return;
+  if (g2 < GRAD_PHI_MIN * GRAD_PHI_MIN) return;
   const double gn = sqrt(g2);
   for (int i = 0; i < Q; i++) {
     const double cg = CV[i][0] * gphi[0] + CV[i][1] * gphi[1] + CV[i][2] * gphi[2];
@@ -300,7 +303,7 @@ void oracle_recolour(double rho_r, double rho_b, double beta, double alpha_bar, 
   const double gn = sqrt(g2);
   for (int i = 0; i < Q; i++) {
     double cosv = 0.0;
-    if (i != 0 && g2 != 0.0) {
+    if (i != 0 && g2 >= GRAD_PHI_MIN * GRAD_PHI_MIN) {
       const double cg = CV[i][0] * gphi[0] + CV[i][1] * gphi[1] + CV[i][2] * gphi[2];
       cosv = cg / (sqrt((double)shell(i)) * gn);
     }

@@ -1,0 +1,506 @@
+// lbm_capi.hip -- host side of the C ABI declared in include/lbm.h: parameter checks,
+// device buffers, the step loop and the read-back entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_cell.h"
+#include "lbm_device.h"
+#include "lbm_kernels.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+  lbm_params p;
+  hipStream_t stream = nullptr;
+  Geo geo{};
+  PullConst pc{};
+  CollideParams cp{};
+  GroupRates rates{};
+  size_t elem = 4;          // bytes per stored population
+  void* g[2] = {nullptr, nullptr};
+  float* sc[2] = {nullptr, nullptr};
+  float* outlet[2] = {nullptr, nullptr};
+  float* init = nullptr;    // initial fields, needed until the first step
+  double* dbuf = nullptr;   // read-back staging
+  size_t dbuf_bytes = 0;
+  double* diag_part = nullptr;
+  double* diag_out = nullptr;
+  long long diag_blocks = 0;
+  int cur = 0;              // index of the state holding the current time
+  int out_cur = 0;          // index of the outlet record of the latest time
+  long long step = 0;
+  bool initialised = false;
+  int tx = 32, ty = 4, zchunk = 16;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
+  std::string err;
+};
+
+static std::string g_create_error;
+
+static lbm_status fail(lbm_ctx* c, lbm_status st, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_error = msg;
+  return st;
+}
+
+static lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
+  return fail(c, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define LBM_HIP(ctx, call)                          \
+  do {                                              \
+    hipError_t e_ = (call);                         \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+static const double kAlphaB = 8.0 / 27.0;
+
+// Validation of lbm_params; fills the derived constants.
+static lbm_status check_params(const lbm_params* p, lbm_ctx* c, std::string& msg) {
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return msg = "lattice sizes must be >= 1", LBM_EINVAL;
+  const long long plane = (long long)p->nx * p->ny;
+  if (plane * Q >= (1LL << 31)) return msg = "nx*ny too large for 32-bit plane offsets", LBM_EINVAL;
+  if (!(p->rho_r0 > 0.0) || !(p->rho_b0 > 0.0)) return msg = "rho_r0 and rho_b0 must be > 0", LBM_EINVAL;
+  const double alpha_r = 1.0 - (1.0 - kAlphaB) * p->rho_b0 / p->rho_r0;
+  if (!(alpha_r >= 0.0 && alpha_r < 1.0))
+    return msg = "density ratio gives alpha_r outside [0,1) (gamma must be >= 19/27)", LBM_EINVAL;
+  if (!(p->nu_r > 0.0) || !(p->nu_b > 0.0)) return msg = "viscosities must be > 0", LBM_EINVAL;
+  if (!(p->A >= 0.0)) return msg = "A must be >= 0", LBM_EINVAL;
+  if (!(p->beta >= 0.0 && p->beta <= 1.0)) return msg = "beta must lie in [0, 1]", LBM_EINVAL;
+  for (int d = 0; d < 2; ++d)
+    if (p->face[2 * d] != LBM_PERIODIC || p->face[2 * d + 1] != LBM_PERIODIC)
+      return msg = "x and y faces must be periodic", LBM_EINVAL;
+  const int lo = p->face[4], hi = p->face[5];
+  if (lo < 0 || lo > 2 || hi < 0 || hi > 3) return msg = "invalid z face rule", LBM_EINVAL;
+  if ((lo == LBM_PERIODIC) != (hi == LBM_PERIODIC)) return msg = "periodic z faces must be paired", LBM_EINVAL;
+  if (lo != LBM_PERIODIC && p->nz < 3) return msg = "nz must be >= 3 with walls in z", LBM_EINVAL;
+  if (p->force != 0 && p->force != 1) return msg = "force must be 0 or 1", LBM_EINVAL;
+  if (p->storage < LBM_F32 || p->storage > LBM_BF16) return msg = "invalid storage", LBM_EINVAL;
+  // relaxation rates: all zero -> the set of Sec. II; otherwise the grouped structure of K
+  bool user = false;
+  for (int j = 0; j < Q; ++j) user |= (p->s[j] != 0.0);
+  GroupRates r{1.5f, 1.5f, 1.83f, 1.4f, 1.61f, 1.98f, 1.98f, 1.74f, 1.74f};
+  if (user) {
+    for (int j = 0; j < 4; ++j)
+      if (p->s[j] != 0.0) return msg = "s[0..3] (conserved moments) must be 0", LBM_EINVAL;
+    const int groups[9][3] = {{4, 4, 4},    {10, 12, 12}, {13, 15, 15}, {16, 16, 16}, {17, 17, 17},
+                              {18, 19, 19}, {20, 22, 22}, {23, 25, 25}, {26, 26, 26}};
+    float* out[9] = {&r.s5, &r.s11, &r.s14, &r.s17, &r.s18, &r.s19, &r.s21, &r.s24, &r.s27};
+    for (int gi = 0; gi < 9; ++gi) {
+      const double v = p->s[groups[gi][0]];
+      for (int j = groups[gi][0]; j <= groups[gi][1]; ++j)
+        if (p->s[j] != v) return msg = "relaxation rates must be equal within each group of K", LBM_EINVAL;
+      if (!(v > 0.0 && v < 2.0)) return msg = "relaxation rates must lie in (0, 2)", LBM_EINVAL;
+      *out[gi] = (float)v;
+    }
+  }
+  if (c) {
+    c->rates = r;
+    c->pc.alpha_r = (float)alpha_r;
+    c->pc.alpha_b = (float)kAlphaB;
+    c->pc.dalpha = (float)(alpha_r - kAlphaB);
+    c->pc.E0 = (float)(p->rho_b0 * (1.0 - kAlphaB));
+    c->cp.alpha_r = (float)alpha_r;
+    c->cp.alpha_b = (float)kAlphaB;
+    c->cp.nu_r = (float)p->nu_r;
+    c->cp.nu_b = (float)p->nu_b;
+    c->cp.A = (float)p->A;
+    c->cp.beta = (float)p->beta;
+    c->cp.force = p->force;
+    c->cp.gx = (float)p->g[0];
+    c->cp.gy = (float)p->g[1];
+    c->cp.gz = (float)p->g[2];
+    c->cp.rho_ref = (float)p->rho_ref;
+    Geo& G = c->geo;
+    G.nx = p->nx;
+    G.ny = p->ny;
+    G.nz = p->nz;
+    G.plane = p->nx * p->ny;
+    G.n = plane * p->nz;
+    G.face_lo = lo;
+    G.face_hi = hi;
+    G.inflow = 0;
+    c->elem = p->storage == LBM_F32 ? 4 : 2;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_create(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
+  if (!params || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+  *out = nullptr;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+  c->p = *params;
+  std::string msg;
+  lbm_status st = check_params(params, c, msg);
+  if (st != LBM_OK) {
+    delete c;
+    return fail(nullptr, st, msg);
+  }
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    delete c;
+    return fail(nullptr, LBM_EDEVICE, "no HIP device");
+  }
+  const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
+  bool ok = true;
+  for (int k = 0; k < 2 && ok; ++k) {
+    ok &= hipMalloc(&c->g[k], n * Q * c->elem) == hipSuccess;
+    ok &= hipMalloc((void**)&c->sc[k], n * 5 * sizeof(float)) == hipSuccess;
+    if (c->geo.face_hi == FACE_OUTFLOW)
+      ok &= hipMalloc((void**)&c->outlet[k], plane * kOutletPlanes * sizeof(float)) == hipSuccess;
+  }
+  c->diag_blocks = (long long)((n + 255) / 256);
+  ok = ok && hipMalloc((void**)&c->diag_part, (size_t)c->diag_blocks * 8 * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->diag_out, 8 * sizeof(double)) == hipSuccess;
+  ok = ok && hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess;
+  if (!ok) {
+    lbm_destroy(c);
+    return fail(nullptr, LBM_ENOMEM, "device allocation failed");
+  }
+  // default tiling: 32 x 4 tiles, z chunks sized for several workgroups per CU
+  const long long tiles = (long long)((c->geo.nx + 31) / 32) * ((c->geo.ny + 3) / 4);
+  int zc = 16;
+  while (zc > 4 && tiles * ((c->geo.nz + zc - 1) / zc) < 2048) zc /= 2;
+  c->zchunk = zc;
+  *out = c;
+  return LBM_OK;
+}
+
+extern "C" void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  for (int k = 0; k < 2; ++k) {
+    if (c->g[k]) (void)hipFree(c->g[k]);
+    if (c->sc[k]) (void)hipFree(c->sc[k]);
+    if (c->outlet[k]) (void)hipFree(c->outlet[k]);
+  }
+  if (c->init) (void)hipFree(c->init);
+  if (c->dbuf) (void)hipFree(c->dbuf);
+  if (c->diag_part) (void)hipFree(c->diag_part);
+  if (c->diag_out) (void)hipFree(c->diag_out);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+extern "C" const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+extern "C" lbm_status lbm_set_inflow(lbm_ctx* c, double xc, double yc, double diameter, double u_normal,
+                                     double noise_rel, unsigned long long seed) {
+  if (!c) return LBM_EINVAL;
+  if (c->geo.face_lo != FACE_FREESLIP && c->geo.face_lo != FACE_BOUNCEBACK)
+    return fail(c, LBM_EINVAL, "the inflow disk needs a wall rule on the -z face");
+  if (!(diameter > 0.0) || !(noise_rel >= 0.0 && noise_rel < 1.0)) return fail(c, LBM_EINVAL, "bad inflow parameters");
+  Geo& G = c->geo;
+  G.inflow = 1;
+  G.xc = (float)xc;
+  G.yc = (float)yc;
+  G.r2 = (float)(0.25 * diameter * diameter);
+  G.rho_r0 = (float)c->p.rho_r0;
+  G.u_in = (float)u_normal;
+  G.noise = (float)noise_rel;
+  G.seed = seed;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_tiling(lbm_ctx* c, int tx, int ty, int zchunk) {
+  if (!c) return LBM_EINVAL;
+  if (!step_tiling_supported(tx, ty) || zchunk < 1) return fail(c, LBM_EINVAL, "unsupported tiling");
+  c->tx = tx;
+  c->ty = ty;
+  c->zchunk = zchunk;
+  return LBM_OK;
+}
+
+static AuxArgs aux_args(const lbm_ctx* c) {
+  AuxArgs a{};
+  a.g_in = c->g[c->cur];
+  a.sc_in = c->sc[c->cur];
+  a.init = c->init;
+  a.outlet_in = c->outlet[c->out_cur];
+  a.outlet_out = c->outlet[1 - c->out_cur];
+  a.step = c->step;
+  a.init_mode = c->step == 0 ? 1 : 0;
+  a.geo = c->geo;
+  a.pc = c->pc;
+  a.cp = c->cp;
+  return a;
+}
+
+extern "C" lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_r, const double* rho_b, const double* u) {
+  if (!c || !rho_r || !rho_b) return LBM_EINVAL;
+  const size_t n = (size_t)c->geo.n;
+  // held as (e, psi, u): e = sum_k rho_k (1 - alpha_k) - E0 formed in FP64; psi the signed
+  // minority-colour fraction (psi_encode)
+  const double ar = 1.0 - (1.0 - kAlphaB) * c->p.rho_b0 / c->p.rho_r0, E0 = c->p.rho_b0 * (1.0 - kAlphaB);
+  std::vector<float> h(5 * n, 0.0f);
+  for (size_t k = 0; k < n; ++k) {
+    if (!(rho_r[k] >= 0.0) || !(rho_b[k] >= 0.0) || !(rho_r[k] + rho_b[k] > 0.0))
+      return fail(c, LBM_EINVAL, "initial densities must be >= 0 with a positive sum");
+    h[k] = (float)(rho_r[k] * (1.0 - ar) + rho_b[k] * (1.0 - kAlphaB) - E0);
+    const double rho = rho_r[k] + rho_b[k];
+    h[n + k] = rho_r[k] <= rho_b[k] ? (float)(rho_r[k] / rho) : -(float)(rho_b[k] / rho);
+    if (u)
+      for (int d = 0; d < 3; ++d) h[(2 + d) * n + k] = (float)u[d * n + k];
+  }
+  if (!c->init) LBM_HIP(c, hipMalloc((void**)&c->init, 5 * n * sizeof(float)));
+  LBM_HIP(c, hipMemcpyAsync(c->init, h.data(), 5 * n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
+  c->cur = 0;
+  c->out_cur = 0;
+  c->step = 0;
+  c->initialised = true;
+  return LBM_OK;
+}
+
+static lbm_status enqueue_one(lbm_ctx* c) {
+  Geo& G = c->geo;
+  const bool init = c->step == 0;
+  if (G.face_hi == FACE_OUTFLOW) {
+    AuxArgs a = aux_args(c);
+    hipError_t e = launch_outlet((int)c->p.storage, a, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "outlet kernel");
+  }
+  StepArgs s{};
+  s.g_in = c->g[c->cur];
+  s.sc_in = c->sc[c->cur];
+  s.g_out = c->g[1 - c->cur];
+  s.sc_out = c->sc[1 - c->cur];
+  s.init = c->init;
+  s.outlet = c->outlet[1 - c->out_cur];
+  s.step = c->step;
+  s.init_mode = init ? 1 : 0;
+  s.zchunk = c->zchunk;
+  s.tiles_x = (G.nx + c->tx - 1) / c->tx;
+  s.tiles_y = (G.ny + c->ty - 1) / c->ty;
+  s.nchunks = (G.nz + c->zchunk - 1) / c->zchunk;
+  s.geo = G;
+  s.pc = c->pc;
+  s.cp = c->cp;
+  s.rates = c->rates;
+  hipError_t e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "step kernel");
+  c->cur = 1 - c->cur;
+  if (G.face_hi == FACE_OUTFLOW) c->out_cur = 1 - c->out_cur;
+  c->step++;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_ctx* c, int nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  if (!c->initialised) return fail(c, LBM_ESTATE, "lbm_step before lbm_init_fields");
+  if (nsteps == 0) return LBM_OK;
+  LBM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  for (int k = 0; k < nsteps; ++k) {
+    lbm_status st = enqueue_one(c);
+    if (st != LBM_OK) return st;
+  }
+  LBM_HIP(c, hipEventRecord(c->ev1, c->stream));
+  c->last_ms = -(double)nsteps;  // resolved lazily: negative = steps of a pending measurement
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_sync(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+extern "C" double lbm_last_step_kernel_ms(const lbm_ctx* cc) {
+  lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+  if (!c) return 0.0;
+  if (c->last_ms < 0.0) {
+    const double steps = -c->last_ms;
+    float ms = 0.0f;
+    if (hipEventSynchronize(c->ev1) != hipSuccess || hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) return 0.0;
+    c->last_ms = ms / steps;
+  }
+  return c->last_ms;
+}
+
+extern "C" long long lbm_step_count(const lbm_ctx* c) { return c ? c->step : -1; }
+
+static lbm_status ensure_dbuf(lbm_ctx* c, size_t bytes) {
+  if (c->dbuf_bytes >= bytes) return LBM_OK;
+  if (c->dbuf) (void)hipFree(c->dbuf);
+  c->dbuf = nullptr;
+  c->dbuf_bytes = 0;
+  LBM_HIP(c, hipMalloc((void**)&c->dbuf, bytes));
+  c->dbuf_bytes = bytes;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_read_field_box(lbm_ctx* c, int field, int x0, int y0, int z0, int wx, int wy, int wz,
+                                         double* dst) {
+  if (!c || !dst) return LBM_EINVAL;
+  if (!c->initialised) return fail(c, LBM_ESTATE, "read before lbm_init_fields");
+  if (field < 0 || field > 6) return fail(c, LBM_EINVAL, "unknown field");
+  const Geo& G = c->geo;
+  if (x0 < 0 || y0 < 0 || z0 < 0 || wx < 1 || wy < 1 || wz < 1 || x0 + wx > G.nx || y0 + wy > G.ny || z0 + wz > G.nz)
+    return fail(c, LBM_EINVAL, "box outside the lattice");
+  const size_t nb = (size_t)wx * wy * wz;
+  // the box is done in z slices so the FP64 staging stays bounded
+  const int zs = (int)std::max<size_t>(1, std::min<size_t>((size_t)wz, (64ull << 20) / ((size_t)wx * wy)));
+  lbm_status st = ensure_dbuf(c, (size_t)wx * wy * zs * 7 * sizeof(double));
+  if (st != LBM_OK) return st;
+  AuxArgs a = aux_args(c);
+  for (int z = 0; z < wz; z += zs) {
+    const int h = std::min(zs, wz - z);
+    const size_t ns = (size_t)wx * wy * h;
+    hipError_t e = launch_fields((int)c->p.storage, a, x0, y0, z0 + z, wx, wy, h, c->dbuf, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fields kernel");
+    LBM_HIP(c, hipMemcpyAsync(dst + (size_t)z * wx * wy, c->dbuf + (size_t)field * ns, ns * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  (void)nb;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_read_field(lbm_ctx* c, int field, double* dst) {
+  if (!c) return LBM_EINVAL;
+  return lbm_read_field_box(c, field, 0, 0, 0, c->geo.nx, c->geo.ny, c->geo.nz, dst);
+}
+
+extern "C" lbm_status lbm_read_populations(lbm_ctx* c, double* dst) {
+  if (!c || !dst) return LBM_EINVAL;
+  if (!c->initialised) return fail(c, LBM_ESTATE, "read before lbm_init_fields");
+  const size_t n = (size_t)c->geo.n;
+  lbm_status st = ensure_dbuf(c, n * 2 * Q * sizeof(double));
+  if (st != LBM_OK) return st;
+  AuxArgs a = aux_args(c);
+  hipError_t e = launch_populations((int)c->p.storage, a, c->dbuf, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "populations kernel");
+  LBM_HIP(c, hipMemcpyAsync(dst, c->dbuf, n * 2 * Q * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_diagnostics(lbm_ctx* c, double xc, double yc, double zc, double r_in, double r_out,
+                                      lbm_diag* out) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->initialised) return fail(c, LBM_ESTATE, "diagnostics before lbm_init_fields");
+  AuxArgs a = aux_args(c);
+  DiagQuery q{xc, yc, zc, r_in, r_out};
+  hipError_t e = launch_diag((int)c->p.storage, a, q, c->diag_part, c->diag_blocks, c->diag_out, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics kernel");
+  double h[8];
+  LBM_HIP(c, hipMemcpyAsync(h, c->diag_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
+  out->mass_r = h[0];
+  out->mass_b = h[1];
+  out->n_in = (long long)h[3];
+  out->p_in = h[3] > 0 ? h[2] / h[3] : 0.0;
+  out->n_out = (long long)h[5];
+  out->p_out = h[5] > 0 ? h[4] / h[5] : 0.0;
+  out->nan_cells = (long long)h[6];
+  out->umax = h[7];
+  out->step = c->step;
+  return out->nan_cells > 0 ? fail(c, LBM_EUNSTABLE, "state holds NaN or non-positive density") : LBM_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint
+extern "C" size_t lbm_state_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
+  size_t b = 64 + n * Q * c->elem + n * 5 * sizeof(float) + n * 5 * sizeof(float);
+  if (c->geo.face_hi == FACE_OUTFLOW) b += plane * kOutletPlanes * sizeof(float);
+  return b;
+}
+
+extern "C" lbm_status lbm_save_state(lbm_ctx* c, void* dst, size_t bytes) {
+  if (!c || !dst) return LBM_EINVAL;
+  if (!c->initialised) return fail(c, LBM_ESTATE, "save before lbm_init_fields");
+  if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
+  const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
+  char* p = static_cast<char*>(dst);
+  std::memset(p, 0, 64);
+  std::memcpy(p, "LBMD3Q27", 8);
+  std::memcpy(p + 8, &c->step, sizeof(long long));
+  p += 64;
+  LBM_HIP(c, hipMemcpyAsync(p, c->g[c->cur], n * Q * c->elem, hipMemcpyDeviceToHost, c->stream));
+  p += n * Q * c->elem;
+  LBM_HIP(c, hipMemcpyAsync(p, c->sc[c->cur], n * 5 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  p += n * 5 * sizeof(float);
+  if (c->init)
+    LBM_HIP(c, hipMemcpyAsync(p, c->init, n * 5 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  p += n * 5 * sizeof(float);
+  if (c->geo.face_hi == FACE_OUTFLOW)
+    LBM_HIP(c, hipMemcpyAsync(p, c->outlet[c->out_cur], plane * kOutletPlanes * sizeof(float), hipMemcpyDeviceToHost,
+                              c->stream));
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_load_state(lbm_ctx* c, const void* src, size_t bytes) {
+  if (!c || !src) return LBM_EINVAL;
+  if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
+  const char* p = static_cast<const char*>(src);
+  if (std::memcmp(p, "LBMD3Q27", 8) != 0) return fail(c, LBM_EINVAL, "not a saved state");
+  long long step;
+  std::memcpy(&step, p + 8, sizeof(long long));
+  const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
+  p += 64;
+  c->cur = 0;
+  c->out_cur = 0;
+  LBM_HIP(c, hipMemcpyAsync(c->g[0], p, n * Q * c->elem, hipMemcpyHostToDevice, c->stream));
+  p += n * Q * c->elem;
+  LBM_HIP(c, hipMemcpyAsync(c->sc[0], p, n * 5 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  p += n * 5 * sizeof(float);
+  if (!c->init) LBM_HIP(c, hipMalloc((void**)&c->init, n * 5 * sizeof(float)));
+  LBM_HIP(c, hipMemcpyAsync(c->init, p, n * 5 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  p += n * 5 * sizeof(float);
+  if (c->geo.face_hi == FACE_OUTFLOW)
+    LBM_HIP(c, hipMemcpyAsync(c->outlet[0], p, plane * kOutletPlanes * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
+  c->step = step;
+  c->initialised = true;
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------- host self-check
+extern "C" lbm_status lbm_selftest_collide_host(const lbm_params* params, const double* fr, const double* fb,
+                                                const double* grad_phi, const double* grad_rho, double* out_r,
+                                                double* out_b) {
+  if (!params || !fr || !fb || !grad_phi || !grad_rho || !out_r || !out_b) return LBM_EINVAL;
+  lbm_ctx tmp;
+  tmp.p = *params;
+  std::string msg;
+  lbm_status st = check_params(params, &tmp, msg);
+  if (st != LBM_OK) return fail(nullptr, st, msg);
+  double rr = 0.0, rb = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    rr += fr[i];
+    rb += fb[i];
+  }
+  const double rho = rr + rb, a = rr / rho;
+  const double abar = tmp.pc.alpha_b + a * (tmp.pc.alpha_r - tmp.pc.alpha_b);
+  float df[Q];
+  for (int i = 0; i < Q; ++i) {
+    const double ph = i == 0 ? abar : (1.0 - abar) * q_of(i);
+    df[i] = (float)(fr[i] + fb[i] - rho * ph);
+  }
+  const float gp[3] = {(float)grad_phi[0], (float)grad_phi[1], (float)grad_phi[2]};
+  const float gr[3] = {(float)grad_rho[0], (float)grad_rho[1], (float)grad_rho[2]};
+  CellOut o;
+  collide_cell(tmp.cp, tmp.rates, df, 0.0f, 0.0f, (float)rho, (float)rr, (float)rb, gp, gr, o);
+  const double ab2 = tmp.pc.alpha_b + (double)o.a * (tmp.pc.alpha_r - tmp.pc.alpha_b);
+  for (int i = 0; i < Q; ++i) {
+    const double ph = i == 0 ? ab2 : (1.0 - ab2) * q_of(i);
+    const double f = (double)o.g[i] + (double)o.rho * ph;
+    const double fri = (double)o.a * f + qc_of(i) * (CX[i] * (double)o.wx + CY[i] * (double)o.wy + CZ[i] * (double)o.wz);
+    out_r[i] = fri;
+    out_b[i] = f - fri;
+  }
+  return LBM_OK;
+}

@@ -1,0 +1,56 @@
+// lbm_dispatch.hip -- storage-type dispatch of the kernel launchers.
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+bool step_tiling_supported(int tx, int ty) { return (tx == 32 && (ty == 4 || ty == 8)) || (tx == 64 && ty == 4); }
+
+
+hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_step_T<float>(a, tx, ty, s);
+    case 1: return launch_step_T<_Float16>(a, tx, ty, s);
+    case 2: return launch_step_T<bf16>(a, tx, ty, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_outlet(int storage, const AuxArgs& a, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_outlet_T<float>(a, s);
+    case 1: return launch_outlet_T<_Float16>(a, s);
+    case 2: return launch_outlet_T<bf16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fields(int storage, const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
+                         hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_fields_T<float>(a, x0, y0, z0, wx, wy, wz, out, s);
+    case 1: return launch_fields_T<_Float16>(a, x0, y0, z0, wx, wy, wz, out, s);
+    case 2: return launch_fields_T<bf16>(a, x0, y0, z0, wx, wy, wz, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_populations(int storage, const AuxArgs& a, double* out, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_populations_T<float>(a, out, s);
+    case 1: return launch_populations_T<_Float16>(a, out, s);
+    case 2: return launch_populations_T<bf16>(a, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_diag(int storage, const AuxArgs& a, const DiagQuery& q, double* part, long long nblocks,
+                       double* out, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_diag_T<float>(a, q, part, nblocks, out, s);
+    case 1: return launch_diag_T<_Float16>(a, q, part, nblocks, out, s);
+    case 2: return launch_diag_T<bf16>(a, q, part, nblocks, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

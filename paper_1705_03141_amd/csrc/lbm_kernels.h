@@ -1,0 +1,82 @@
+// lbm_kernels.h -- launch-side view of the kernels (argument blocks and launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_cell.h"
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Thread layout of the step kernel: TX*TY interior threads (one per cell of the tile) plus
+// whole waves for the 2(TX+2) + 2 TY cells of the halo ring.
+template <int TX, int TY>
+struct StepShape {
+  static constexpr int kInterior = TX * TY;
+  static constexpr int kHalo = 2 * (TX + 2) + 2 * TY;
+  static constexpr int kThreads = kInterior + ((kHalo + 63) / 64) * 64;
+  // register budget: aim for at least two workgroups per CU
+  static constexpr int kWaves = kThreads / 64;
+  static constexpr int kMinWavesPerSimd = (2 * kWaves + 3) / 4 < 2 ? 2 : (2 * kWaves + 3) / 4;
+  static_assert(kInterior % 64 == 0, "interior must be whole waves");
+  static_assert(kThreads <= 1024, "workgroup too large");
+};
+
+struct StepArgs {
+  const void* g_in;      // populations written by the previous step (storage type)
+  const float* sc_in;    // scalars written by the previous step
+  void* g_out;
+  float* sc_out;
+  const float* init;     // init mode: rho_r, rho_b, ux, uy, uz planes of ncells floats
+  const float* outlet;   // outlet record of the current time (outflow face only)
+  long long step;
+  int init_mode;
+  int zchunk, tiles_x, tiles_y, nchunks;
+  Geo geo;
+  PullConst pc;
+  CollideParams cp;
+  GroupRates rates;
+};
+
+// Arguments of the outlet and read-back kernels.
+struct AuxArgs {
+  const void* g_in;
+  const float* sc_in;
+  const float* init;
+  const float* outlet_in;  // outlet record of the previous time
+  float* outlet_out;       // outlet record of the current time
+  long long step;
+  int init_mode;
+  Geo geo;
+  PullConst pc;
+  CollideParams cp;
+};
+
+struct DiagQuery {
+  double xc, yc, zc, r_in, r_out;
+};
+
+// Typed launchers, instantiated once per storage type (lbm_storage_*.hip).
+template <typename T>
+hipError_t launch_step_T(const StepArgs& a, int tx, int ty, hipStream_t s);
+template <typename T>
+hipError_t launch_outlet_T(const AuxArgs& a, hipStream_t s);
+template <typename T>
+hipError_t launch_fields_T(const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_populations_T(const AuxArgs& a, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, long long nblocks, double* out,
+                         hipStream_t s);
+
+// Dispatch on the storage code of lbm_params (0 FP32, 1 FP16, 2 BF16).
+bool step_tiling_supported(int tx, int ty);
+hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream_t s);
+hipError_t launch_outlet(int storage, const AuxArgs& a, hipStream_t s);
+hipError_t launch_fields(int storage, const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
+                         hipStream_t s);
+hipError_t launch_populations(int storage, const AuxArgs& a, double* out, hipStream_t s);
+hipError_t launch_diag(int storage, const AuxArgs& a, const DiagQuery& q, double* part, long long nblocks,
+                       double* out, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,829 @@
+// lbm_kernels_impl.h -- gfx950 kernels of the D3Q27 colour-fluid lattice Boltzmann step.
+//
+// step_kernel: one fused pass per time step.  A workgroup owns a TX x TY column of cells
+// and marches through a chunk of z planes.  Per plane it (1) stages the per-cell scalars of
+// the next source plane (with a 2-cell halo) into LDS, (2) pulls the 27 incoming
+// populations of every cell of the plane plus a 1-cell halo ring, rebuilding the colour
+// densities of time t (Sec. II, Eq. (order)), and writes phi and rho into an LDS ring of 3
+// planes, and (3) collides the previous plane: isotropic gradient stencil from the LDS ring,
+// MRT collision with enhanced equilibrium and forcing, perturbation and recolouring
+// (lbm_cell.h), then stores 27 deviations + 5 scalars per cell.  Streaming is implicit in
+// the pull of the next step.  Each population is read once from HBM per step (halo pulls
+// hit L2) and written once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "lbm_device.h"
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+__device__ __forceinline__ int slot3(int q) { return ((q % 3) + 3) % 3; }
+
+// Neighbourhood addressing of a cell: source z planes (wrapped when z is periodic, clamped
+// otherwise; clamped entries are never read), row offsets y nx and columns x, all wrapped in
+// x and y.
+struct Nbr {
+  int zs[3];
+  int row[3];
+  int xs[3];
+};
+
+__device__ __forceinline__ Nbr neighbours(const Geo& G, int x, int y, int z) {
+  Nbr b;
+  const bool per = G.face_lo == FACE_PERIODIC;
+  b.zs[0] = z == 0 ? (per ? G.nz - 1 : 0) : z - 1;
+  b.zs[1] = z;
+  b.zs[2] = z == G.nz - 1 ? (per ? 0 : G.nz - 1) : z + 1;
+  b.row[0] = (y == 0 ? G.ny - 1 : y - 1) * G.nx;
+  b.row[1] = y * G.nx;
+  b.row[2] = (y == G.ny - 1 ? 0 : y + 1) * G.nx;
+  b.xs[0] = x == 0 ? G.nx - 1 : x - 1;
+  b.xs[1] = x;
+  b.xs[2] = x == G.nx - 1 ? 0 : x + 1;
+  return b;
+}
+
+// Population J of the cell at reader + (dx, dy, dz).
+template <typename T>
+__device__ __forceinline__ float load_pop(const Geo& G, const T* __restrict__ g, const Nbr& b, int j, int dx, int dy,
+                                          int dz) {
+  const T* slab = g + (size_t)(b.zs[dz + 1] * Q + j) * (size_t)G.plane;
+  return Codec<T>::dec(slab[b.row[dy + 1] + b.xs[dx + 1]]);
+}
+
+// Pull of one cell in a plane of pull mode MODE.  Scalars of the source cells come from
+// `acc`:  acc.self_e(), acc.self_psi()  e and psi of the reader at t-1;
+//         acc.e/psi/w(dx, dy, dz)        e, psi, w of the cell at reader + (dx, dy, dz).
+// Returns rho, rho_r, rho_b and e of time t; with WANT_DF also the deviations in the reader's
+// form d_i = g_i(src) + q_i (e(src) - e(self)) (from the rest equilibrium of the previous
+// state) with shift = E(t-1) - E(t) and drho = sum_i d_i that move them to the present one
+// (collide_cell takes them so; to_deviation() applies them).  Everything is formed from
+// increments so that no O(1) quantity is subtracted from another, and the colour that is the
+// reader's minority is accumulated from its own fractions.
+template <typename T, bool WANT_DF, int MODE, typename Acc>
+__device__ __forceinline__ void pull_cell(const Geo& G, const PullConst& C, const T* __restrict__ g, const Nbr& b,
+                                          const Acc& acc, float& rho, float& rho_r, float& rho_b, float& e_new,
+                                          float (&df)[Q], float& shift_out, float& drho_out) {
+  const float e_self = acc.self_e(), psi_self = acc.self_psi();
+  const bool track_red = !psi_red_major(psi_self);  // the reader's minority colour
+  const float a_self = psi_a(psi_self);
+  const float t_self = track_red ? psi_self : -psi_self;  // fraction of the tracked colour
+  const float rho_old = rho_of(C, e_self, a_self);
+  const float E_self = C.E0 + e_self;
+  const float sgn = track_red ? 1.0f : -1.0f;  // recolouring adds to red, removes from blue
+  // rest population: its source is the reader itself
+  float d_rho = load_pop<T>(G, g, b, 0, 0, 0, 0);
+  float d_t = t_self * d_rho;
+  if constexpr (WANT_DF) df[0] = d_rho;
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr Src s = resolve<i, MODE>();
+    const float gv = load_pop<T>(G, g, b, s.j, s.dx, s.dy, s.dz);
+    const float de = acc.e(s.dx, s.dy, s.dz) - e_self, psi = acc.psi(s.dx, s.dy, s.dz);
+    const float t = track_red ? psi_a(psi) : psi_b(psi);
+    float cw = 0.0f;  // c_j . w of the source, only the non-zero components
+    if constexpr (s.ccx != 0) cw += (float)s.ccx * acc.w(0, s.dx, s.dy, s.dz);
+    if constexpr (s.ccy != 0) cw += (float)s.ccy * acc.w(1, s.dx, s.dy, s.dz);
+    if constexpr (s.ccz != 0) cw += (float)s.ccz * acc.w(2, s.dx, s.dy, s.dz);
+    const float d = gv + q_of(i) * de;
+    d_rho += d;
+    d_t += t * d + q_of(i) * E_self * (t - t_self) + sgn * qc_of(i) * cw;
+    if constexpr (WANT_DF) df[i] = d;
+    if constexpr (i % 9 == 0) __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight
+  });
+  rho = rho_old + d_rho;
+  const float rho_t = t_self * rho_old + d_t, rho_o = rho - rho_t;
+  rho_r = track_red ? rho_t : rho_o;
+  rho_b = track_red ? rho_o : rho_t;
+  // E = (1 - alpha_b) rho - (alpha_r - alpha_b) rho_r is linear: its increment is exact
+  const float d_rhor = track_red ? d_t : d_rho - d_t;
+  const float shift = C.dalpha * d_rhor - (1.0f - C.alpha_b) * d_rho;  // E(t-1) - E(t)
+  e_new = e_self - shift;
+  shift_out = shift;
+  drho_out = d_rho;
+}
+
+// Total deviations df_i = f_i - rho varphi_i(alpha_bar) from the reader's form.
+__device__ __forceinline__ void to_deviation(float (&df)[Q], float shift) {
+  float sum = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    df[i] += q_of(i) * shift;
+    sum += df[i];
+  }
+  df[0] = -sum;  // sum_i df_i = 0 exactly
+}
+
+// Scalars from the LDS planes of the step kernel.
+template <int SX, int SY>
+struct LdsAcc {
+  const float (*sE)[SY][SX];
+  const float (*sA)[SY][SX];
+  const float (*sW)[3][SY][SX];
+  int px, py;   // reader position in the staged plane (offset by the 2-cell halo)
+  int slot[3];  // LDS slots of the planes z-1, z, z+1
+  __device__ __forceinline__ float self_e() const { return sE[slot[1]][py][px]; }
+  __device__ __forceinline__ float self_psi() const { return sA[slot[1]][py][px]; }
+  __device__ __forceinline__ float e(int dx, int dy, int dz) const { return sE[slot[dz + 1]][py + dy][px + dx]; }
+  __device__ __forceinline__ float psi(int dx, int dy, int dz) const { return sA[slot[dz + 1]][py + dy][px + dx]; }
+  __device__ __forceinline__ float w(int k, int dx, int dy, int dz) const {
+    return sW[slot[dz + 1]][k][py + dy][px + dx];
+  }
+};
+
+// Scalars straight from HBM (small kernels).
+struct GlobalAcc {
+  const float* sc;
+  const Geo* G;
+  const Nbr* b;
+  __device__ __forceinline__ float val(int k, int dx, int dy, int dz) const {
+    return sc[(size_t)(b->zs[dz + 1] * 5 + k) * (size_t)G->plane + b->row[dy + 1] + b->xs[dx + 1]];
+  }
+  __device__ __forceinline__ float self_e() const { return val(0, 0, 0, 0); }
+  __device__ __forceinline__ float self_psi() const { return val(1, 0, 0, 0); }
+  __device__ __forceinline__ float e(int dx, int dy, int dz) const { return val(0, dx, dy, dz); }
+  __device__ __forceinline__ float psi(int dx, int dy, int dz) const { return val(1, dx, dy, dz); }
+  __device__ __forceinline__ float w(int k, int dx, int dy, int dz) const { return val(2 + k, dx, dy, dz); }
+};
+
+// Dispatch of the pull on the plane's mode (uniform across the workgroup).
+template <typename T, bool WANT_DF, typename Acc>
+__device__ __forceinline__ void pull_any(int mode, const Geo& G, const PullConst& C, const T* __restrict__ g,
+                                         const Nbr& b, const Acc& acc, float& rho, float& rho_r, float& rho_b,
+                                         float& e, float (&df)[Q], float& shift, float& drho) {
+  switch (mode) {
+    case kLoBB: pull_cell<T, WANT_DF, kLoBB>(G, C, g, b, acc, rho, rho_r, rho_b, e, df, shift, drho); break;
+    case kLoFS: pull_cell<T, WANT_DF, kLoFS>(G, C, g, b, acc, rho, rho_r, rho_b, e, df, shift, drho); break;
+    case kHiBB: pull_cell<T, WANT_DF, kHiBB>(G, C, g, b, acc, rho, rho_r, rho_b, e, df, shift, drho); break;
+    case kHiFS: pull_cell<T, WANT_DF, kHiFS>(G, C, g, b, acc, rho, rho_r, rho_b, e, df, shift, drho); break;
+    default: pull_cell<T, WANT_DF, kBulk>(G, C, g, b, acc, rho, rho_r, rho_b, e, df, shift, drho); break;
+  }
+}
+
+// Isotropic gradient of Sec. II, 3 sum_i w_i chi(x + c_i) c_i, from a 3x3x3 neighbourhood
+// v[dz+1][dy+1][dx+1]: weights 2/9, 1/18, 1/72 on the axis, edge and corner differences.
+__device__ __forceinline__ void gradient27(const float (&v)[3][3][3], float (&gr)[3]) {
+  const float c1 = 2.0f / 9.0f, c2 = 1.0f / 18.0f, c3 = 1.0f / 72.0f;
+  float D[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) D[a][b] = v[a][b][2] - v[a][b][0];
+  gr[0] = c1 * D[1][1] + c2 * (D[0][1] + D[2][1] + D[1][0] + D[1][2]) + c3 * (D[0][0] + D[0][2] + D[2][0] + D[2][2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) D[a][b] = v[a][2][b] - v[a][0][b];
+  gr[1] = c1 * D[1][1] + c2 * (D[0][1] + D[2][1] + D[1][0] + D[1][2]) + c3 * (D[0][0] + D[0][2] + D[2][0] + D[2][2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) D[a][b] = v[2][a][b] - v[0][a][b];
+  gr[2] = c1 * D[1][1] + c2 * (D[0][1] + D[2][1] + D[1][0] + D[1][2]) + c3 * (D[0][0] + D[0][2] + D[2][0] + D[2][2]);
+}
+
+// Initial state at a cell (reading R1): each colour at its equilibrium with Phi = 0, so the
+// total deviation is rho w_i [3 c.u + 9/2 (c.u)^2 - 3/2 u^2].  The initial fields are held as
+// (e, psi, ux, uy, uz), planes of ncells floats.
+template <bool WANT_DF>
+__device__ __forceinline__ void init_cell(const float* __restrict__ init, const PullConst& C, long long n,
+                                          long long c, float& rho, float& rho_r, float& rho_b, float& e,
+                                          float (&df)[Q]) {
+  e = init[c];
+  const float psi = init[n + c];
+  rho = rho_of(C, e, psi_a(psi));
+  rho_r = psi_a(psi) * rho;
+  rho_b = psi_b(psi) * rho;
+  if constexpr (WANT_DF) {
+    const float ux = init[2 * n + c], uy = init[3 * n + c], uz = init[4 * n + c];
+    const float r = rho;
+    static_for<0, Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      df[i] = eq_dev<i>(r, ux, uy, uz);
+    });
+  }
+}
+
+// Outlet-plane record at a column: total deviations, e and the colour densities.
+template <bool WANT_DF>
+__device__ __forceinline__ void outlet_cell(const float* __restrict__ outlet, const PullConst& C, int plane, int col,
+                                            float& rho, float& rho_r, float& rho_b, float& e, float (&df)[Q]) {
+  // The record does not depend on the plane counter; without this the compiler hoists its
+  // 54 loads out of the plane loop and keeps them live across the whole march.
+  asm volatile("" : "+v"(col));
+  e = outlet[54 * plane + col];
+  const float psi = outlet[55 * plane + col];
+  rho = rho_of(C, e, psi_a(psi));
+  rho_r = psi_a(psi) * rho;
+  rho_b = psi_b(psi) * rho;
+  if constexpr (WANT_DF) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) df[i] = outlet[i * plane + col] + outlet[(Q + i) * plane + col];
+  }
+}
+
+// ================================================================== step kernel
+// INIT selects the first step after lbm_init_fields, whose pre-collision state is the
+// per-colour equilibrium of the initial fields rather than a pull of stored populations.
+template <typename T, int TX, int TY, bool INIT>
+__global__ void __launch_bounds__((StepShape<TX, TY>::kThreads), (StepShape<TX, TY>::kMinWavesPerSimd))
+    step_kernel(const StepArgs A) {
+  using Shape = StepShape<TX, TY>;
+  constexpr int SX = TX + 4, SY = TY + 4, DX = TX + 2, DY = TY + 2;
+  constexpr int NI = Shape::kInterior, NH = Shape::kHalo, NT = Shape::kThreads;
+  __shared__ float sE[3][SY][SX], sA[3][SY][SX], sW[3][3][SY][SX];
+  __shared__ float dPhi[3][DY][DX], dRho[3][DY][DX];
+  // deviations of the next plane, parked by each interior thread while it collides the current one
+  __shared__ float stash[Q][NI];
+
+  const Geo& G = A.geo;
+  const bool zper = G.face_lo == FACE_PERIODIC;
+  const bool outflow = G.face_hi == FACE_OUTFLOW;
+  const T* __restrict__ gin = static_cast<const T*>(A.g_in);
+  T* __restrict__ gout = static_cast<T*>(A.g_out);
+  const int plane = G.plane;
+
+  // block -> tile and z chunk
+  int bid = blockIdx.x;
+  const int chunk = bid % A.nchunks;
+  bid /= A.nchunks;
+  const int tyi = bid % A.tiles_y, txi = bid / A.tiles_y;
+  const int x0 = txi * TX, y0 = tyi * TY;
+  const int z0 = chunk * A.zchunk, z1 = min(z0 + A.zchunk, G.nz);
+
+  // thread -> cell of the plane: interior cells first, then the halo ring
+  const int tid = threadIdx.x;
+  const bool interior = tid < NI;
+  int lx, ly;
+  bool puller = true;
+  if (interior) {
+    lx = tid % TX;
+    ly = tid / TX;
+  } else {
+    const int h = tid - NI;
+    puller = h < NH;
+    if (h < TX + 2) {
+      lx = h - 1;
+      ly = -1;
+    } else if (h < 2 * (TX + 2)) {
+      lx = h - (TX + 2) - 1;
+      ly = TY;
+    } else if (h < 2 * (TX + 2) + TY) {
+      lx = -1;
+      ly = h - 2 * (TX + 2);
+    } else {
+      lx = TX;
+      ly = min(h - 2 * (TX + 2) - TY, TY - 1);
+    }
+  }
+  const int gx = wrap(x0 + lx, G.nx), gy = wrap(y0 + ly, G.ny);
+  const bool live = interior && (x0 + lx < G.nx) && (y0 + ly < G.ny);
+  const int col = gy * G.nx + gx;
+
+  auto stage = [&](int q) {
+    if constexpr (INIT) return;
+    const int zq = zper ? wrap(q, G.nz) : min(max(q, 0), G.nz - 1);
+    const int s = slot3(q);
+    const float* base = A.sc_in + (size_t)zq * 5 * (size_t)plane;
+    for (int k = tid; k < SX * SY; k += NT) {
+      const int sx = k % SX, sy = k / SX;
+      const int c = wrap(y0 + sy - 2, G.ny) * G.nx + wrap(x0 + sx - 2, G.nx);
+      sE[s][sy][sx] = base[c];
+      sA[s][sy][sx] = base[plane + c];
+      sW[s][0][sy][sx] = base[2 * plane + c];
+      sW[s][1][sy][sx] = base[3 * plane + c];
+      sW[s][2][sy][sx] = base[4 * plane + c];
+    }
+  };
+
+  // Pull of plane counter q: densities into the LDS ring; interior threads also leave the
+  // deviations df and e of their cell.
+  auto pull = [&](int q, float& rho, float& rho_r, float& rho_b, float& e, float (&df)[Q], float& shift,
+                  float& drho, auto want_df) {
+    constexpr bool WANT = decltype(want_df)::value;
+    const int z = zper ? wrap(q, G.nz) : q;
+    shift = 0.0f;
+    drho = 0.0f;
+    if constexpr (INIT) {
+      init_cell<WANT>(A.init, A.pc, G.n, (long long)z * plane + col, rho, rho_r, rho_b, e, df);
+    } else {
+      if (outflow && z == G.nz - 1) {
+        outlet_cell<WANT>(A.outlet, A.pc, plane, col, rho, rho_r, rho_b, e, df);
+      } else {
+        const Nbr b = neighbours(G, gx, gy, z);
+        LdsAcc<SX, SY> acc{sE, sA, sW, lx + 2, ly + 2, {slot3(q - 1), slot3(q), slot3(q + 1)}};
+        pull_any<T, WANT>(plane_mode(G, z), G, A.pc, gin, b, acc, rho, rho_r, rho_b, e, df, shift, drho);
+      }
+    }
+    if (is_inflow(G, gx, gy, z)) {  // R10: inflow sites are pure red at rho_r0
+      rho = G.rho_r0;
+      rho_r = G.rho_r0;
+      rho_b = 0.0f;
+    }
+    const int s = slot3(q);
+    dPhi[s][ly + 1][lx + 1] = (rho_r - rho_b) / rho;
+    dRho[s][ly + 1][lx + 1] = rho;
+  };
+
+  auto needs_pull = [&](int q) { return zper || (q >= 0 && q < G.nz); };
+
+  float df[Q];
+  float rho = 1.0f, rho_r = 0.0f, rho_b = 1.0f, e = 0.0f, shift = 0.0f, drho = 0.0f;  // plane p
+
+  // prologue: plane z0-1 (densities only), then z0 (interior threads keep df)
+  stage(z0 - 2);
+  stage(z0 - 1);
+  stage(z0);
+  __syncthreads();
+  if (puller && needs_pull(z0 - 1)) pull(z0 - 1, rho, rho_r, rho_b, e, df, shift, drho, std::false_type{});
+  __syncthreads();
+  stage(z0 + 1);
+  __syncthreads();
+  if (puller) {
+    if (interior)
+      pull(z0, rho, rho_r, rho_b, e, df, shift, drho, std::true_type{});
+    else
+      pull(z0, rho, rho_r, rho_b, e, df, shift, drho, std::false_type{});
+  }
+  if (interior) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) stash[i][tid] = df[i];
+  }
+  __syncthreads();
+
+  for (int p = z0; p < z1; ++p) {
+    stage(p + 2);
+    __syncthreads();
+    float rhon = 1.0f, rho_rn = 0.0f, rho_bn = 1.0f, en = 0.0f, shiftn = 0.0f, drhon = 0.0f;
+    if (puller && needs_pull(p + 1)) {
+      if (interior)
+        pull(p + 1, rhon, rho_rn, rho_bn, en, df, shiftn, drhon, std::true_type{});
+      else
+        pull(p + 1, rhon, rho_rn, rho_bn, en, df, shiftn, drhon, std::false_type{});
+    }
+    __syncthreads();
+    if (interior) {
+      // swap: plane p's deviations out of the stash, plane p+1's in (own slots only)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const float t = stash[i][tid];
+        stash[i][tid] = df[i];
+        df[i] = t;
+      }
+    }
+    if (live) {
+      const size_t cell = (size_t)p * plane + col;
+      T* gslab = gout + (size_t)p * Q * (size_t)plane;
+      float* sslab = A.sc_out + (size_t)p * 5 * (size_t)plane;
+      if (is_inflow(G, gx, gy, p)) {
+        // inflow site: emit the red equilibrium at rho_r0, u_in e_z (R10)
+        const float u = inflow_speed(G, (long long)cell, A.step);
+        static_for<0, Q>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          gslab[i * plane + col] = Codec<T>::enc(eq_dev<i>(G.rho_r0, 0.0f, 0.0f, u));
+        });
+        sslab[col] = 0.0f;  // rho_r0 (1 - alpha_r) = E0 exactly
+        sslab[plane + col] = -0.0f;  // pure red
+        sslab[2 * plane + col] = 0.0f;
+        sslab[3 * plane + col] = 0.0f;
+        sslab[4 * plane + col] = 0.0f;
+      } else {
+        const int sm = (!zper && p == 0) ? slot3(p) : slot3(p - 1);
+        const int sp = (!zper && p == G.nz - 1) ? slot3(p) : slot3(p + 1);
+        const int s0 = slot3(p);
+        float gp[3], gr[3];
+        {
+          float v[3][3][3];
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+              v[0][dy][dx] = dPhi[sm][ly + dy][lx + dx];
+              v[1][dy][dx] = dPhi[s0][ly + dy][lx + dx];
+              v[2][dy][dx] = dPhi[sp][ly + dy][lx + dx];
+            }
+          gradient27(v, gp);
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+              v[0][dy][dx] = dRho[sm][ly + dy][lx + dx];
+              v[1][dy][dx] = dRho[s0][ly + dy][lx + dx];
+              v[2][dy][dx] = dRho[sp][ly + dy][lx + dx];
+            }
+          gradient27(v, gr);
+        }
+        CellOut o;
+        collide_cell(A.cp, A.rates, df, shift, drho, rho, rho_r, rho_b, gp, gr, o);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) gslab[i * plane + col] = Codec<T>::enc(o.g[i]);
+        sslab[col] = e;
+        sslab[plane + col] = psi_encode(rho_r, rho_b, rho);
+        sslab[2 * plane + col] = o.wx;
+        sslab[3 * plane + col] = o.wy;
+        sslab[4 * plane + col] = o.wz;
+      }
+    }
+    rho = rhon;
+    rho_r = rho_rn;
+    rho_b = rho_bn;
+    e = en;
+    shift = shiftn;
+    drho = drhon;
+  }
+}
+
+// ================================================================== outlet and read-back
+// Per-colour pre-collision populations of a cell from the stored state (no LDS).
+template <typename T>
+__device__ __forceinline__ void pull_colours(const AuxArgs& A, int x, int y, int z, float (&fr)[Q], float (&fb)[Q]) {
+  const Geo& G = A.geo;
+  const Nbr b = neighbours(G, x, y, z);
+  GlobalAcc acc{A.sc_in, &A.geo, &b};
+  const T* g = static_cast<const T*>(A.g_in);
+  const float e_self = acc.self_e(), psi_self = acc.self_psi();
+  const float rho_self = rho_of(A.pc, e_self, psi_a(psi_self));
+  auto one = [&](auto ic, auto mode) {
+    constexpr int i = decltype(ic)::value;
+    constexpr Src s = resolve<i, decltype(mode)::value>();
+    const float gv = load_pop<T>(G, g, b, s.j, s.dx, s.dy, s.dz);
+    if constexpr (i == 0) {
+      const float f0 = gv + rho_self - (A.pc.E0 + e_self);  // g_0 + rho alpha_bar
+      fr[0] = psi_a(psi_self) * f0;
+      fb[0] = psi_b(psi_self) * f0;
+    } else {
+      const float fi = gv + q_of(i) * (A.pc.E0 + acc.e(s.dx, s.dy, s.dz));
+      float cw = 0.0f;
+      if constexpr (s.ccx != 0) cw += (float)s.ccx * acc.w(0, s.dx, s.dy, s.dz);
+      if constexpr (s.ccy != 0) cw += (float)s.ccy * acc.w(1, s.dx, s.dy, s.dz);
+      if constexpr (s.ccz != 0) cw += (float)s.ccz * acc.w(2, s.dx, s.dy, s.dz);
+      const float psi = acc.psi(s.dx, s.dy, s.dz);
+      fr[i] = psi_a(psi) * fi + qc_of(i) * cw;
+      fb[i] = psi_b(psi) * fi - qc_of(i) * cw;
+    }
+  };
+  switch (plane_mode(G, z)) {
+    case kLoBB: static_for<0, Q>([&](auto ic) { one(ic, std::integral_constant<int, kLoBB>{}); }); break;
+    case kLoFS: static_for<0, Q>([&](auto ic) { one(ic, std::integral_constant<int, kLoFS>{}); }); break;
+    case kHiBB: static_for<0, Q>([&](auto ic) { one(ic, std::integral_constant<int, kHiBB>{}); }); break;
+    case kHiFS: static_for<0, Q>([&](auto ic) { one(ic, std::integral_constant<int, kHiFS>{}); }); break;
+    default: static_for<0, Q>([&](auto ic) { one(ic, std::integral_constant<int, kBulk>{}); }); break;
+  }
+}
+
+// Moments (increment form, as in the step) and per-colour populations of a bulk cell.
+template <typename T>
+__device__ __forceinline__ void pull_global(const AuxArgs& A, int x, int y, int z, float& rho, float& rho_r,
+                                            float& rho_b, float& e, float (&df)[Q]) {
+  const Nbr b = neighbours(A.geo, x, y, z);
+  GlobalAcc acc{A.sc_in, &A.geo, &b};
+  float shift, drho;
+  pull_any<T, true>(plane_mode(A.geo, z), A.geo, A.pc, static_cast<const T*>(A.g_in), b, acc, rho, rho_r, rho_b, e,
+                    df, shift, drho);
+  to_deviation(df, shift);
+}
+
+__device__ __forceinline__ float varphi_of(int i, float alpha) { return i == 0 ? alpha : (1.0f - alpha) * q_of(i); }
+
+// Convective outflow (R11): per column, the outlet plane's pre-collision state of time t is
+// [state(t-1) + lambda f(N-1, t)] / (1 + lambda), colour by colour and population by
+// population, lambda = max(0, u_z(N-1, t)).  Returned as deviations from each colour's
+// rest equilibrium, dr_i = f^r_i - rho_r varphi_i(alpha_r) (likewise blue), and (e, psi).
+template <typename T>
+__device__ void outlet_state(const AuxArgs& A, int x, int y, float (&dr)[Q], float (&db)[Q], float& e_out,
+                             float& psi_out) {
+  const Geo& G = A.geo;
+  const int plane = G.plane, col = y * G.nx + x;
+  if (A.init_mode) {
+    const long long c = (long long)(G.nz - 1) * plane + col;
+    float rho, rho_r, rho_b, e, df[Q];
+    init_cell<false>(A.init, A.pc, G.n, c, rho, rho_r, rho_b, e, df);
+    const float ux = A.init[2 * G.n + c], uy = A.init[3 * G.n + c], uz = A.init[4 * G.n + c];
+    const float r_ = rho_r, b_ = rho_b;
+    static_for<0, Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      dr[i] = eq_dev<i>(r_, ux, uy, uz);
+      db[i] = eq_dev<i>(b_, ux, uy, uz);
+    });
+    e_out = e;
+    psi_out = A.init[G.n + c];
+    return;
+  }
+  // the cell below the outlet at time t
+  const int z = G.nz - 2;
+  float rho, rho_r, rho_b, e_b, df[Q];
+  pull_global<T>(A, x, y, z, rho, rho_r, rho_b, e_b, df);
+  float fr[Q], fb[Q];
+  pull_colours<T>(A, x, y, z, fr, fb);
+  float jz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) jz += (float)CZ[i] * df[i];
+  float Fz = 0.0f;
+  if (A.cp.force) Fz = (rho - A.cp.rho_ref) * A.cp.gz;
+  float lam = (jz + 0.5f * Fz) / rho;
+  lam = lam > 0.0f ? lam : 0.0f;
+  const float inv = 1.0f / (1.0f + lam);
+  // the minority colour's deviations directly, the majority's as the rest of the total
+  const bool red_minor = rho_r <= rho_b;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    float dri, dbi;
+    if (red_minor) {
+      dri = fr[i] - rho_r * varphi_of(i, A.pc.alpha_r);
+      dbi = df[i] - dri;
+    } else {
+      dbi = fb[i] - rho_b * varphi_of(i, A.pc.alpha_b);
+      dri = df[i] - dbi;
+    }
+    dr[i] = (A.outlet_in[i * plane + col] + lam * dri) * inv;
+    db[i] = (A.outlet_in[(Q + i) * plane + col] + lam * dbi) * inv;
+  }
+  const float e_prev = A.outlet_in[54 * plane + col], psi_prev = A.outlet_in[55 * plane + col];
+  const float rho_prev = rho_of(A.pc, e_prev, psi_a(psi_prev));
+  const float rr = (psi_a(psi_prev) * rho_prev + lam * rho_r) * inv;
+  const float rb = (psi_b(psi_prev) * rho_prev + lam * rho_b) * inv;
+  e_out = (e_prev + lam * e_b) * inv;
+  psi_out = psi_encode(rr, rb, rr + rb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) outlet_kernel(const AuxArgs A) {
+  const Geo& G = A.geo;
+  const int plane = G.plane;
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= plane) return;
+  float dr[Q], db[Q], e, psi;
+  outlet_state<T>(A, col % G.nx, col / G.nx, dr, db, e, psi);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    A.outlet_out[i * plane + col] = dr[i];
+    A.outlet_out[(Q + i) * plane + col] = db[i];
+  }
+  A.outlet_out[54 * plane + col] = e;
+  A.outlet_out[55 * plane + col] = psi;
+}
+
+// Densities, momentum sum_i f_i c_i and (optionally) per-colour pre-collision populations of
+// one cell at the current time.
+template <typename T>
+__device__ void cell_state(const AuxArgs& A, int x, int y, int z, float& rho, float& rho_r, float& rho_b,
+                           float (&j)[3], float (&fr)[Q], float (&fb)[Q], bool want_pops) {
+  const Geo& G = A.geo;
+  const long long c = (long long)z * G.plane + (long long)y * G.nx + x;
+  const float ar = A.pc.alpha_r, ab = A.pc.alpha_b;
+  if (is_inflow(G, x, y, z)) {
+    const float u = inflow_speed(G, c, A.step);
+    rho = rho_r = G.rho_r0;
+    rho_b = 0.0f;
+    j[0] = j[1] = 0.0f;
+    j[2] = G.rho_r0 * u;  // read-back reports the set velocity (no F/2 shift)
+    if (want_pops) {
+      static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        fr[i] = G.rho_r0 * varphi_of(i, ar) + eq_dev<i>(G.rho_r0, 0.0f, 0.0f, u);
+        fb[i] = 0.0f;
+      });
+    }
+    return;
+  }
+  if (A.init_mode || (G.face_hi == FACE_OUTFLOW && z == G.nz - 1)) {
+    float dr[Q], db[Q], e, psi;
+    if (A.init_mode) {
+      float df[Q];
+      init_cell<false>(A.init, A.pc, G.n, c, rho, rho_r, rho_b, e, df);
+      const float ux = A.init[2 * G.n + c], uy = A.init[3 * G.n + c], uz = A.init[4 * G.n + c];
+      const float r_ = rho_r, b_ = rho_b;
+      static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dr[i] = eq_dev<i>(r_, ux, uy, uz);
+        db[i] = eq_dev<i>(b_, ux, uy, uz);
+      });
+    } else {
+      outlet_state<T>(A, x, y, dr, db, e, psi);
+      rho = rho_of(A.pc, e, psi_a(psi));
+      rho_r = psi_a(psi) * rho;
+      rho_b = psi_b(psi) * rho;
+    }
+    j[0] = j[1] = j[2] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float d = dr[i] + db[i];
+      j[0] += (float)CX[i] * d;
+      j[1] += (float)CY[i] * d;
+      j[2] += (float)CZ[i] * d;
+      if (want_pops) {
+        fr[i] = dr[i] + rho_r * varphi_of(i, ar);
+        fb[i] = db[i] + rho_b * varphi_of(i, ab);
+      }
+    }
+    return;
+  }
+  // bulk cell: moments exactly as the step kernel forms them, populations rebuilt per colour
+  float df[Q], e;
+  pull_global<T>(A, x, y, z, rho, rho_r, rho_b, e, df);
+  j[0] = j[1] = j[2] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    j[0] += (float)CX[i] * df[i];
+    j[1] += (float)CY[i] * df[i];
+    j[2] += (float)CZ[i] * df[i];
+  }
+  if (want_pops) pull_colours<T>(A, x, y, z, fr, fb);
+}
+
+__device__ __forceinline__ void body_force(const AuxArgs& A, float rho, float (&F)[3]) {
+  F[0] = F[1] = F[2] = 0.0f;
+  if (A.cp.force) {
+    const float dr = rho - A.cp.rho_ref;
+    F[0] = dr * A.cp.gx;
+    F[1] = dr * A.cp.gy;
+    F[2] = dr * A.cp.gz;
+  }
+}
+
+// Macroscopic fields of a box: out[field][cell of box] in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) fields_kernel(const AuxArgs A, int x0, int y0, int z0, int wx, int wy, int wz,
+                                                     double* __restrict__ out) {
+  const long long nb = (long long)wx * wy * wz;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  const int x = x0 + (int)(k % wx), y = y0 + (int)((k / wx) % wy), z = z0 + (int)(k / ((long long)wx * wy));
+  float rho, rho_r, rho_b, j[3], fr[Q], fb[Q];
+  cell_state<T>(A, x, y, z, rho, rho_r, rho_b, j, fr, fb, false);
+  float F[3];
+  body_force(A, rho, F);
+  if (is_inflow(A.geo, x, y, z)) F[0] = F[1] = F[2] = 0.0f;
+  const double r = rho, rr = rho_r, rb = rho_b;
+  out[k] = rr;
+  out[nb + k] = rb;
+  out[2 * nb + k] = ((double)j[0] + 0.5 * F[0]) / r;
+  out[3 * nb + k] = ((double)j[1] + 0.5 * F[1]) / r;
+  out[4 * nb + k] = ((double)j[2] + 0.5 * F[2]) / r;
+  out[5 * nb + k] = (rr - rb) / r;
+  out[6 * nb + k] = rr * 9.0 * (1.0 - (double)A.pc.alpha_r) / 19.0 + rb * 9.0 * (1.0 - (double)A.pc.alpha_b) / 19.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) populations_kernel(const AuxArgs A, double* __restrict__ out) {
+  const Geo& G = A.geo;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.n) return;
+  const int x = (int)(c % G.nx), y = (int)((c / G.nx) % G.ny), z = (int)(c / G.plane);
+  float rho, rho_r, rho_b, j[3], fr[Q], fb[Q];
+  cell_state<T>(A, x, y, z, rho, rho_r, rho_b, j, fr, fb, true);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    out[(long long)i * G.n + c] = fr[i];
+    out[(long long)(Q + i) * G.n + c] = fb[i];
+  }
+}
+
+// Diagnostics: per-block FP64 partial sums, reduced in a fixed order by a second kernel.
+//   part[b] = {mass_r, mass_b, p_in, n_in, p_out, n_out, bad cells, umax}
+template <typename T>
+__global__ void __launch_bounds__(256) diag_kernel(const AuxArgs A, DiagQuery Qy, double* __restrict__ part) {
+  const Geo& G = A.geo;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (c < G.n) {
+    const int x = (int)(c % G.nx), y = (int)((c / G.nx) % G.ny), z = (int)(c / G.plane);
+    float rho, rho_r, rho_b, j[3], fr[Q], fb[Q];
+    cell_state<T>(A, x, y, z, rho, rho_r, rho_b, j, fr, fb, false);
+    const double rr = rho_r, rb = rho_b;
+    float F[3];
+    body_force(A, rho, F);
+    if (is_inflow(G, x, y, z)) F[0] = F[1] = F[2] = 0.0f;
+    const double ux = ((double)j[0] + 0.5 * F[0]) / rho, uy = ((double)j[1] + 0.5 * F[1]) / rho,
+                 uz = ((double)j[2] + 0.5 * F[2]) / rho;
+    const double p = rr * 9.0 * (1.0 - (double)A.pc.alpha_r) / 19.0 + rb * 9.0 * (1.0 - (double)A.pc.alpha_b) / 19.0;
+    const double dx = x - Qy.xc, dy = y - Qy.yc, dz = z - Qy.zc;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const bool bad = !(rho > 0.0f) || isnan(rho_r) || isnan(rho_b) || isnan(j[0]) || isnan(j[1]) || isnan(j[2]);
+    v[0] = rr;
+    v[1] = rb;
+    if (r <= Qy.r_in) {
+      v[2] = p;
+      v[3] = 1.0;
+    }
+    if (r >= Qy.r_out) {
+      v[4] = p;
+      v[5] = 1.0;
+    }
+    v[6] = bad ? 1.0 : 0.0;
+    v[7] = bad ? 0.0 : sqrt(ux * ux + uy * uy + uz * uz);
+  }
+  // wave64 butterfly reduction, then across the 4 waves through LDS
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double o = __shfl_xor(v[k], off, 64);
+      v[k] = (k == 7) ? fmax(v[k], o) : v[k] + o;
+    }
+  }
+  __shared__ double red[4][8];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0)
+    for (int k = 0; k < 8; ++k) red[wave][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    double s = red[0][k];
+    for (int w = 1; w < 4; ++w) s = (k == 7) ? fmax(s, red[w][k]) : s + red[w][k];
+    part[(long long)blockIdx.x * 8 + k] = s;
+  }
+}
+
+static __global__ void __launch_bounds__(256) diag_finish_kernel(const double* __restrict__ part, long long nblocks,
+                                                          double* __restrict__ out) {
+  // fixed-order reduction: thread t sums blocks t, t+256, ...; then a tree over threads
+  __shared__ double red[256][8];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long b = threadIdx.x; b < nblocks; b += 256)
+    for (int k = 0; k < 8; ++k) v[k] = (k == 7) ? fmax(v[k], part[b * 8 + k]) : v[k] + part[b * 8 + k];
+  for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = v[k];
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 8; ++k)
+        red[threadIdx.x][k] = (k == 7) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                                       : red[threadIdx.x][k] + red[threadIdx.x + s][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) out[threadIdx.x] = red[0][threadIdx.x];
+}
+
+// ================================================================== launchers (per storage type)
+template <typename T, int TX, int TY>
+hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
+  const long long blocks = (long long)a.tiles_x * a.tiles_y * a.nchunks;
+  if (a.init_mode)
+    hipLaunchKernelGGL((step_kernel<T, TX, TY, true>), dim3((unsigned)blocks), dim3(StepShape<TX, TY>::kThreads), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL((step_kernel<T, TX, TY, false>), dim3((unsigned)blocks), dim3(StepShape<TX, TY>::kThreads), 0,
+                       s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_T(const StepArgs& a, int tx, int ty, hipStream_t s) {
+  if (tx == 32 && ty == 4) return launch_step_tile<T, 32, 4>(a, s);
+  if (tx == 32 && ty == 8) return launch_step_tile<T, 32, 8>(a, s);
+  if (tx == 64 && ty == 4) return launch_step_tile<T, 64, 4>(a, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_outlet_T(const AuxArgs& a, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.geo.plane + 255) / 256);
+  hipLaunchKernelGGL(outlet_kernel<T>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fields_T(const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
+                           hipStream_t s) {
+  const long long nb = (long long)wx * wy * wz;
+  hipLaunchKernelGGL(fields_kernel<T>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, a, x0, y0, z0, wx, wy, wz,
+                     out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_populations_T(const AuxArgs& a, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(populations_kernel<T>, dim3((unsigned)((a.geo.n + 255) / 256)), dim3(256), 0, s, a, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, long long nblocks, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(diag_kernel<T>, dim3((unsigned)nblocks), dim3(256), 0, s, a, q, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(256), 0, s, part, nblocks, out);
+  return hipGetLastError();
+}
+
+#define LBM_INSTANTIATE_STORAGE(T)                                                                                \
+  template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t);                                   \
+  template hipError_t launch_outlet_T<T>(const AuxArgs&, hipStream_t);                                            \
+  template hipError_t launch_fields_T<T>(const AuxArgs&, int, int, int, int, int, int, double*, hipStream_t);    \
+  template hipError_t launch_populations_T<T>(const AuxArgs&, double*, hipStream_t);                              \
+  template hipError_t launch_diag_T<T>(const AuxArgs&, const DiagQuery&, double*, long long, double*, hipStream_t);
+
+}  // namespace lbm

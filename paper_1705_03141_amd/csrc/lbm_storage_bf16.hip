@@ -1,0 +1,6 @@
+// lbm_storage_bf16.hip -- kernels instantiated for bf16 population storage.
+#include "lbm_kernels_impl.h"
+
+namespace lbm {
+LBM_INSTANTIATE_STORAGE(bf16)
+}  // namespace lbm

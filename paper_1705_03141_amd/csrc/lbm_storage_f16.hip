@@ -1,0 +1,6 @@
+// lbm_storage_f16.hip -- kernels instantiated for _Float16 population storage.
+#include "lbm_kernels_impl.h"
+
+namespace lbm {
+LBM_INSTANTIATE_STORAGE(_Float16)
+}  // namespace lbm
