@@ -1,0 +1,190 @@
+"""Benchmark of the D3Q27 colour-fluid step on one MI355X.
+
+Workload: the Rayleigh-Taylor problem on 128 x 128 x 512 (At = 0.5, g = 1e-5, Re = 256,
+seeded single-mode interface), the configuration the throughput metric is quoted on; FP32
+populations and arithmetic.  A "step" is one full time step of the method over the whole
+lattice.  Prints one JSON line:
+
+  value       MLUPS = cells x steps / wall time of the timed steps (inputs resident in HBM)
+  roofline    the step kernel against HBM: achieved = 432 B per cell update (one read and one
+              write of 2 x 27 FP32 populations, the standard two-colour traffic) x cells /
+              mean kernel time from HIP events on the library's stream; peak 8000 GB/s
+  traffic     HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
+              (null when the kernel sources differ from those the counters were taken on)
+  cpu_baseline  the FP64 oracle timed on the host cores on a 128 x 128 x 64 window of the
+              same workload (rank 0, N = 1 only)
+
+Also reported (extra): the FP16- and BF16-storage throughput, the bytes the kernel itself
+must move per update (27 stored deviations + 5 FP32 scalars, read and written once) and
+that fraction of the roofline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_GBS = 8000.0
+# HBM bytes per step-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+# scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000); valid
+# only for the kernel sources they were taken on.
+COUNTERS = {"sources_sha16": "bdb5ef059caae684", "storage": "f32", "fetch_kib": 1573536.0, "fetch_scale": 2.0,
+            "write_kib": 1077248.0, "write_scale": 1.0}
+KERNEL_SOURCES = ["lbm_cell.h", "lbm_device.h", "lbm_kernels.h", "lbm_kernels_impl.h", "lbm_storage_f32.hip"]
+STD_BYTES = 432.0  # 2 colours x 27 populations x 4 B, read + write
+
+
+def state_bytes(storage: str) -> float:
+    elem = 4 if storage == "f32" else 2
+    return 2.0 * (27 * elem + 5 * 4)
+
+
+def run_gpu(pb, storage, steps, warmup):
+    import torch
+    from paper_1705_03141_amd import lbm
+
+    lat = lbm.Lattice(pb, storage=storage)
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    lat.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = lat.last_step_kernel_ms()
+    diag = lat.diagnostics()
+    lat.close()
+    return wall, kernel_ms, diag
+
+
+def kernel_sources_sha16() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_1705_03141_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per launch, or None when the counters were taken on other kernel sources."""
+    c = COUNTERS
+    if storage != c["storage"] or kernel_sources_sha16() != c["sources_sha16"]:
+        return None
+    return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pb_full, steps=30):
+    import numpy as np  # noqa: F401
+    import oracle
+
+    win = pb_full.window(0, 0, pb_full.nz // 2 - 32, pb_full.nx, pb_full.ny, 64)
+    o = oracle.Oracle(win)
+    o.step(1)  # first touch
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": win.ncells * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{win.nx}x{win.ny}x{win.nz} window of the same workload around the interface, {steps} steps, "
+                      f"{dt:.1f} s"}
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+    against nbytes gives the scale of those counters."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": ms,
+                      "GBps_read_plus_write": 2 * nbytes / ms / 1e6}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design only)", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_1705_03141_amd import workloads as W
+
+    pb = W.cfg_rayleigh_taylor()
+    n = pb.ncells
+    log(f"{pb.name} {pb.nx}x{pb.ny}x{pb.nz}, storage {args.storage}, {args.warmup}+{args.steps} steps")
+    wall, kernel_ms, diag = run_gpu(pb, args.storage, args.steps, args.warmup)
+    log(f"{wall * 1e3 / args.steps:.3f} ms/step wall, kernel {kernel_ms:.3f} ms")
+    if diag["unstable"]:
+        print("bench.py: the run went unstable", file=sys.stderr)
+        sys.exit(1)
+    mlups = n * args.steps / wall / 1e6
+    achieved = STD_BYTES * n / (kernel_ms * 1e-3) / 1e9
+    extra = {"kernel_ms": kernel_ms, "state_bytes_per_update": state_bytes(args.storage),
+             "state_traffic_frac": state_bytes(args.storage) * n / (kernel_ms * 1e-3) / 1e9 / PEAK_GBS}
+    for st in ("f16", "bf16"):
+        if st != args.storage and not args.no_extra:
+            w2, k2, _ = run_gpu(pb, st, max(args.steps // 2, 10), args.warmup)
+            log(f"storage {st}: kernel {k2:.3f} ms")
+            extra[f"{st}_mlups"] = n * max(args.steps // 2, 10) / w2 / 1e6
+    line = {
+        "metric": "MLUPS (D3Q27 two-component) and % of HBM roofline; FP16-store vs FP32 at fixed error",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "f32" else f"f32 compute, {args.storage} storage",
+        "data": "synthetic",
+        "config": {"workload": "rayleigh_taylor_128x128x512", "nx": pb.nx, "ny": pb.ny, "nz": pb.nz,
+                   "atwood": 0.5, "g": 1e-5, "reynolds": 256, "storage": args.storage},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_GBS, "traffic": measured_traffic(args.storage)},
+        "extra": extra,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        line["cpu_baseline"] = cpu_baseline(pb)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
