@@ -20,8 +20,10 @@ BUILD = os.path.join(HERE, "_build")
 UNITS = ["lbm_storage_f32.hip", "lbm_storage_f16.hip", "lbm_storage_bf16.hip", "lbm_dispatch.hip", "lbm_capi.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are disabled: the compiler still vectorises plain float code.
+# FMA contraction is decided per source expression (-ffp-contract=on): every inlined copy of
+# a function then rounds identically, which keeps results independent of the tiling.
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
-         "-packed-fp32-ops", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
+         "-packed-fp32-ops", "-ffp-contract=on", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 
 
 def hipcc() -> str:

@@ -36,7 +36,7 @@ struct lbm_ctx {
   int out_cur = 0;          // index of the outlet record of the latest time
   long long step = 0;
   bool initialised = false;
-  int tx = 32, ty = 4, zchunk = 16;
+  int tx = 32, ty = 8, zchunk = 0;  // zchunk 0: chosen from the resident workgroups
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   std::string err;
@@ -168,11 +168,6 @@ extern "C" lbm_status lbm_create(const lbm_params* params, void* hip_stream, lbm
     lbm_destroy(c);
     return fail(nullptr, LBM_ENOMEM, "device allocation failed");
   }
-  // default tiling: 32 x 4 tiles, z chunks sized for several workgroups per CU
-  const long long tiles = (long long)((c->geo.nx + 31) / 32) * ((c->geo.ny + 3) / 4);
-  int zc = 16;
-  while (zc > 4 && tiles * ((c->geo.nz + zc - 1) / zc) < 2048) zc /= 2;
-  c->zchunk = zc;
   *out = c;
   return LBM_OK;
 }
@@ -215,7 +210,7 @@ extern "C" lbm_status lbm_set_inflow(lbm_ctx* c, double xc, double yc, double di
 
 extern "C" lbm_status lbm_set_tiling(lbm_ctx* c, int tx, int ty, int zchunk) {
   if (!c) return LBM_EINVAL;
-  if (!step_tiling_supported(tx, ty) || zchunk < 1) return fail(c, LBM_EINVAL, "unsupported tiling");
+  if (!step_tiling_supported(tx, ty) || zchunk < 0) return fail(c, LBM_EINVAL, "unsupported tiling");
   c->tx = tx;
   c->ty = ty;
   c->zchunk = zchunk;
@@ -263,6 +258,30 @@ extern "C" lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_r, const dou
   return LBM_OK;
 }
 
+// Planes per workgroup when none is set: the number of z chunks that minimises
+// (rounds of resident workgroups) x (planes per chunk + the 2 planes each chunk pulls first).
+static int auto_zchunk(const lbm_ctx* c) {
+  const Geo& G = c->geo;
+  const long long tiles = (long long)((G.nx + c->tx - 1) / c->tx) * ((G.ny + c->ty - 1) / c->ty);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  long long resident = step_resident_blocks((int)c->p.storage, c->tx, c->ty, dev);
+  if (resident < 1) resident = 1024;
+  long long best_cost = -1;
+  int best = G.nz;
+  for (int nch = 1; nch <= G.nz; ++nch) {
+    const int zc = (G.nz + nch - 1) / nch;
+    if ((G.nz + zc - 1) / zc != nch) continue;  // same chunking as a smaller count
+    const long long rounds = (tiles * nch + resident - 1) / resident;
+    const long long cost = rounds * (zc + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = zc;
+    }
+  }
+  return best;
+}
+
 static lbm_status enqueue_one(lbm_ctx* c) {
   Geo& G = c->geo;
   const bool init = c->step == 0;
@@ -280,6 +299,7 @@ static lbm_status enqueue_one(lbm_ctx* c) {
   s.outlet = c->outlet[1 - c->out_cur];
   s.step = c->step;
   s.init_mode = init ? 1 : 0;
+  if (c->zchunk < 1) c->zchunk = auto_zchunk(c);
   s.zchunk = c->zchunk;
   s.tiles_x = (G.nx + c->tx - 1) / c->tx;
   s.tiles_y = (G.ny + c->ty - 1) / c->ty;

@@ -15,6 +15,15 @@ hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream
   return hipErrorInvalidValue;
 }
 
+int step_resident_blocks(int storage, int tx, int ty, int device) {
+  switch (storage) {
+    case 0: return step_resident_blocks_T<float>(tx, ty, device);
+    case 1: return step_resident_blocks_T<_Float16>(tx, ty, device);
+    case 2: return step_resident_blocks_T<bf16>(tx, ty, device);
+  }
+  return 0;
+}
+
 hipError_t launch_outlet(int storage, const AuxArgs& a, hipStream_t s) {
   switch (storage) {
     case 0: return launch_outlet_T<float>(a, s);

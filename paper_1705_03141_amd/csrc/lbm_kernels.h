@@ -8,18 +8,17 @@
 
 namespace lbm {
 
-// Thread layout of the step kernel: TX*TY interior threads (one per cell of the tile) plus
-// whole waves for the 2(TX+2) + 2 TY cells of the halo ring.
+// Thread layout of the step kernel: one thread per cell of a TX x TY tile; the first
+// 2(TX+2) + 2TY threads also pull one cell of the ring around the tile.
 template <int TX, int TY>
-struct StepShape {
-  static constexpr int kInterior = TX * TY;
-  static constexpr int kHalo = 2 * (TX + 2) + 2 * TY;
-  static constexpr int kThreads = kInterior + ((kHalo + 63) / 64) * 64;
-  // register budget: aim for at least two workgroups per CU
-  static constexpr int kWaves = kThreads / 64;
-  static constexpr int kMinWavesPerSimd = (2 * kWaves + 3) / 4 < 2 ? 2 : (2 * kWaves + 3) / 4;
-  static_assert(kInterior % 64 == 0, "interior must be whole waves");
-  static_assert(kThreads <= 1024, "workgroup too large");
+struct StepTile {
+  static constexpr int kThreads = TX * TY;
+  static constexpr int kRing = 2 * (TX + 2) + 2 * TY;
+  static constexpr int SX = TX + 4, SY = TY + 4, kStaged = SX * SY;  // scalars, 2-cell halo
+  static constexpr int DX = TX + 2, DY = TY + 2, kDense = DX * DY;   // densities, 1-cell ring
+  static constexpr int kStagePerThread = (kStaged + kThreads - 1) / kThreads;
+  static_assert(kThreads % 64 == 0, "tile must be whole waves");
+  static_assert(kRing <= kThreads, "ring larger than the tile");
 };
 
 struct StepArgs {
@@ -60,6 +59,8 @@ struct DiagQuery {
 template <typename T>
 hipError_t launch_step_T(const StepArgs& a, int tx, int ty, hipStream_t s);
 template <typename T>
+int step_resident_blocks_T(int tx, int ty, int device);
+template <typename T>
 hipError_t launch_outlet_T(const AuxArgs& a, hipStream_t s);
 template <typename T>
 hipError_t launch_fields_T(const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out, hipStream_t s);
@@ -72,6 +73,8 @@ hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, lon
 // Dispatch on the storage code of lbm_params (0 FP32, 1 FP16, 2 BF16).
 bool step_tiling_supported(int tx, int ty);
 hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream_t s);
+// Workgroups of the step kernel that fit on the device at once (0 if unknown).
+int step_resident_blocks(int storage, int tx, int ty, int device);
 hipError_t launch_outlet(int storage, const AuxArgs& a, hipStream_t s);
 hipError_t launch_fields(int storage, const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
                          hipStream_t s);

@@ -1,15 +1,7 @@
-// lbm_kernels_impl.h -- gfx950 kernels of the D3Q27 colour-fluid lattice Boltzmann step.
-//
-// step_kernel: one fused pass per time step.  A workgroup owns a TX x TY column of cells
-// and marches through a chunk of z planes.  Per plane it (1) stages the per-cell scalars of
-// the next source plane (with a 2-cell halo) into LDS, (2) pulls the 27 incoming
-// populations of every cell of the plane plus a 1-cell halo ring, rebuilding the colour
-// densities of time t (Sec. II, Eq. (order)), and writes phi and rho into an LDS ring of 3
-// planes, and (3) collides the previous plane: isotropic gradient stencil from the LDS ring,
-// MRT collision with enhanced equilibrium and forcing, perturbation and recolouring
-// (lbm_cell.h), then stores 27 deviations + 5 scalars per cell.  Streaming is implicit in
-// the pull of the next step.  Each population is read once from HBM per step (halo pulls
-// hit L2) and written once.
+// lbm_kernels_impl.h -- device building blocks of the D3Q27 colour-fluid step (pull of one
+// cell, isotropic gradient, initial and outlet states) and the small kernels around the step:
+// convective outlet, read-back of fields and populations, FP64 diagnostics.  The fused step
+// kernel itself is in lbm_step.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -126,23 +118,6 @@ __device__ __forceinline__ void to_deviation(float (&df)[Q], float shift) {
   df[0] = -sum;  // sum_i df_i = 0 exactly
 }
 
-// Scalars from the LDS planes of the step kernel.
-template <int SX, int SY>
-struct LdsAcc {
-  const float (*sE)[SY][SX];
-  const float (*sA)[SY][SX];
-  const float (*sW)[3][SY][SX];
-  int px, py;   // reader position in the staged plane (offset by the 2-cell halo)
-  int slot[3];  // LDS slots of the planes z-1, z, z+1
-  __device__ __forceinline__ float self_e() const { return sE[slot[1]][py][px]; }
-  __device__ __forceinline__ float self_psi() const { return sA[slot[1]][py][px]; }
-  __device__ __forceinline__ float e(int dx, int dy, int dz) const { return sE[slot[dz + 1]][py + dy][px + dx]; }
-  __device__ __forceinline__ float psi(int dx, int dy, int dz) const { return sA[slot[dz + 1]][py + dy][px + dx]; }
-  __device__ __forceinline__ float w(int k, int dx, int dy, int dz) const {
-    return sW[slot[dz + 1]][k][py + dy][px + dx];
-  }
-};
-
 // Scalars straight from HBM (small kernels).
 struct GlobalAcc {
   const float* sc;
@@ -231,217 +206,6 @@ __device__ __forceinline__ void outlet_cell(const float* __restrict__ outlet, co
   if constexpr (WANT_DF) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) df[i] = outlet[i * plane + col] + outlet[(Q + i) * plane + col];
-  }
-}
-
-// ================================================================== step kernel
-// INIT selects the first step after lbm_init_fields, whose pre-collision state is the
-// per-colour equilibrium of the initial fields rather than a pull of stored populations.
-template <typename T, int TX, int TY, bool INIT>
-__global__ void __launch_bounds__((StepShape<TX, TY>::kThreads), (StepShape<TX, TY>::kMinWavesPerSimd))
-    step_kernel(const StepArgs A) {
-  using Shape = StepShape<TX, TY>;
-  constexpr int SX = TX + 4, SY = TY + 4, DX = TX + 2, DY = TY + 2;
-  constexpr int NI = Shape::kInterior, NH = Shape::kHalo, NT = Shape::kThreads;
-  __shared__ float sE[3][SY][SX], sA[3][SY][SX], sW[3][3][SY][SX];
-  __shared__ float dPhi[3][DY][DX], dRho[3][DY][DX];
-  // deviations of the next plane, parked by each interior thread while it collides the current one
-  __shared__ float stash[Q][NI];
-
-  const Geo& G = A.geo;
-  const bool zper = G.face_lo == FACE_PERIODIC;
-  const bool outflow = G.face_hi == FACE_OUTFLOW;
-  const T* __restrict__ gin = static_cast<const T*>(A.g_in);
-  T* __restrict__ gout = static_cast<T*>(A.g_out);
-  const int plane = G.plane;
-
-  // block -> tile and z chunk
-  int bid = blockIdx.x;
-  const int chunk = bid % A.nchunks;
-  bid /= A.nchunks;
-  const int tyi = bid % A.tiles_y, txi = bid / A.tiles_y;
-  const int x0 = txi * TX, y0 = tyi * TY;
-  const int z0 = chunk * A.zchunk, z1 = min(z0 + A.zchunk, G.nz);
-
-  // thread -> cell of the plane: interior cells first, then the halo ring
-  const int tid = threadIdx.x;
-  const bool interior = tid < NI;
-  int lx, ly;
-  bool puller = true;
-  if (interior) {
-    lx = tid % TX;
-    ly = tid / TX;
-  } else {
-    const int h = tid - NI;
-    puller = h < NH;
-    if (h < TX + 2) {
-      lx = h - 1;
-      ly = -1;
-    } else if (h < 2 * (TX + 2)) {
-      lx = h - (TX + 2) - 1;
-      ly = TY;
-    } else if (h < 2 * (TX + 2) + TY) {
-      lx = -1;
-      ly = h - 2 * (TX + 2);
-    } else {
-      lx = TX;
-      ly = min(h - 2 * (TX + 2) - TY, TY - 1);
-    }
-  }
-  const int gx = wrap(x0 + lx, G.nx), gy = wrap(y0 + ly, G.ny);
-  const bool live = interior && (x0 + lx < G.nx) && (y0 + ly < G.ny);
-  const int col = gy * G.nx + gx;
-
-  auto stage = [&](int q) {
-    if constexpr (INIT) return;
-    const int zq = zper ? wrap(q, G.nz) : min(max(q, 0), G.nz - 1);
-    const int s = slot3(q);
-    const float* base = A.sc_in + (size_t)zq * 5 * (size_t)plane;
-    for (int k = tid; k < SX * SY; k += NT) {
-      const int sx = k % SX, sy = k / SX;
-      const int c = wrap(y0 + sy - 2, G.ny) * G.nx + wrap(x0 + sx - 2, G.nx);
-      sE[s][sy][sx] = base[c];
-      sA[s][sy][sx] = base[plane + c];
-      sW[s][0][sy][sx] = base[2 * plane + c];
-      sW[s][1][sy][sx] = base[3 * plane + c];
-      sW[s][2][sy][sx] = base[4 * plane + c];
-    }
-  };
-
-  // Pull of plane counter q: densities into the LDS ring; interior threads also leave the
-  // deviations df and e of their cell.
-  auto pull = [&](int q, float& rho, float& rho_r, float& rho_b, float& e, float (&df)[Q], float& shift,
-                  float& drho, auto want_df) {
-    constexpr bool WANT = decltype(want_df)::value;
-    const int z = zper ? wrap(q, G.nz) : q;
-    shift = 0.0f;
-    drho = 0.0f;
-    if constexpr (INIT) {
-      init_cell<WANT>(A.init, A.pc, G.n, (long long)z * plane + col, rho, rho_r, rho_b, e, df);
-    } else {
-      if (outflow && z == G.nz - 1) {
-        outlet_cell<WANT>(A.outlet, A.pc, plane, col, rho, rho_r, rho_b, e, df);
-      } else {
-        const Nbr b = neighbours(G, gx, gy, z);
-        LdsAcc<SX, SY> acc{sE, sA, sW, lx + 2, ly + 2, {slot3(q - 1), slot3(q), slot3(q + 1)}};
-        pull_any<T, WANT>(plane_mode(G, z), G, A.pc, gin, b, acc, rho, rho_r, rho_b, e, df, shift, drho);
-      }
-    }
-    if (is_inflow(G, gx, gy, z)) {  // R10: inflow sites are pure red at rho_r0
-      rho = G.rho_r0;
-      rho_r = G.rho_r0;
-      rho_b = 0.0f;
-    }
-    const int s = slot3(q);
-    dPhi[s][ly + 1][lx + 1] = (rho_r - rho_b) / rho;
-    dRho[s][ly + 1][lx + 1] = rho;
-  };
-
-  auto needs_pull = [&](int q) { return zper || (q >= 0 && q < G.nz); };
-
-  float df[Q];
-  float rho = 1.0f, rho_r = 0.0f, rho_b = 1.0f, e = 0.0f, shift = 0.0f, drho = 0.0f;  // plane p
-
-  // prologue: plane z0-1 (densities only), then z0 (interior threads keep df)
-  stage(z0 - 2);
-  stage(z0 - 1);
-  stage(z0);
-  __syncthreads();
-  if (puller && needs_pull(z0 - 1)) pull(z0 - 1, rho, rho_r, rho_b, e, df, shift, drho, std::false_type{});
-  __syncthreads();
-  stage(z0 + 1);
-  __syncthreads();
-  if (puller) {
-    if (interior)
-      pull(z0, rho, rho_r, rho_b, e, df, shift, drho, std::true_type{});
-    else
-      pull(z0, rho, rho_r, rho_b, e, df, shift, drho, std::false_type{});
-  }
-  if (interior) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) stash[i][tid] = df[i];
-  }
-  __syncthreads();
-
-  for (int p = z0; p < z1; ++p) {
-    stage(p + 2);
-    __syncthreads();
-    float rhon = 1.0f, rho_rn = 0.0f, rho_bn = 1.0f, en = 0.0f, shiftn = 0.0f, drhon = 0.0f;
-    if (puller && needs_pull(p + 1)) {
-      if (interior)
-        pull(p + 1, rhon, rho_rn, rho_bn, en, df, shiftn, drhon, std::true_type{});
-      else
-        pull(p + 1, rhon, rho_rn, rho_bn, en, df, shiftn, drhon, std::false_type{});
-    }
-    __syncthreads();
-    if (interior) {
-      // swap: plane p's deviations out of the stash, plane p+1's in (own slots only)
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const float t = stash[i][tid];
-        stash[i][tid] = df[i];
-        df[i] = t;
-      }
-    }
-    if (live) {
-      const size_t cell = (size_t)p * plane + col;
-      T* gslab = gout + (size_t)p * Q * (size_t)plane;
-      float* sslab = A.sc_out + (size_t)p * 5 * (size_t)plane;
-      if (is_inflow(G, gx, gy, p)) {
-        // inflow site: emit the red equilibrium at rho_r0, u_in e_z (R10)
-        const float u = inflow_speed(G, (long long)cell, A.step);
-        static_for<0, Q>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          gslab[i * plane + col] = Codec<T>::enc(eq_dev<i>(G.rho_r0, 0.0f, 0.0f, u));
-        });
-        sslab[col] = 0.0f;  // rho_r0 (1 - alpha_r) = E0 exactly
-        sslab[plane + col] = -0.0f;  // pure red
-        sslab[2 * plane + col] = 0.0f;
-        sslab[3 * plane + col] = 0.0f;
-        sslab[4 * plane + col] = 0.0f;
-      } else {
-        const int sm = (!zper && p == 0) ? slot3(p) : slot3(p - 1);
-        const int sp = (!zper && p == G.nz - 1) ? slot3(p) : slot3(p + 1);
-        const int s0 = slot3(p);
-        float gp[3], gr[3];
-        {
-          float v[3][3][3];
-#pragma unroll
-          for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-              v[0][dy][dx] = dPhi[sm][ly + dy][lx + dx];
-              v[1][dy][dx] = dPhi[s0][ly + dy][lx + dx];
-              v[2][dy][dx] = dPhi[sp][ly + dy][lx + dx];
-            }
-          gradient27(v, gp);
-#pragma unroll
-          for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-              v[0][dy][dx] = dRho[sm][ly + dy][lx + dx];
-              v[1][dy][dx] = dRho[s0][ly + dy][lx + dx];
-              v[2][dy][dx] = dRho[sp][ly + dy][lx + dx];
-            }
-          gradient27(v, gr);
-        }
-        CellOut o;
-        collide_cell(A.cp, A.rates, df, shift, drho, rho, rho_r, rho_b, gp, gr, o);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) gslab[i * plane + col] = Codec<T>::enc(o.g[i]);
-        sslab[col] = e;
-        sslab[plane + col] = psi_encode(rho_r, rho_b, rho);
-        sslab[2 * plane + col] = o.wx;
-        sslab[3 * plane + col] = o.wy;
-        sslab[4 * plane + col] = o.wz;
-      }
-    }
-    rho = rhon;
-    rho_r = rho_rn;
-    rho_b = rho_bn;
-    e = en;
-    shift = shiftn;
-    drho = drhon;
   }
 }
 
@@ -767,26 +531,6 @@ static __global__ void __launch_bounds__(256) diag_finish_kernel(const double* _
 }
 
 // ================================================================== launchers (per storage type)
-template <typename T, int TX, int TY>
-hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
-  const long long blocks = (long long)a.tiles_x * a.tiles_y * a.nchunks;
-  if (a.init_mode)
-    hipLaunchKernelGGL((step_kernel<T, TX, TY, true>), dim3((unsigned)blocks), dim3(StepShape<TX, TY>::kThreads), 0, s,
-                       a);
-  else
-    hipLaunchKernelGGL((step_kernel<T, TX, TY, false>), dim3((unsigned)blocks), dim3(StepShape<TX, TY>::kThreads), 0,
-                       s, a);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_step_T(const StepArgs& a, int tx, int ty, hipStream_t s) {
-  if (tx == 32 && ty == 4) return launch_step_tile<T, 32, 4>(a, s);
-  if (tx == 32 && ty == 8) return launch_step_tile<T, 32, 8>(a, s);
-  if (tx == 64 && ty == 4) return launch_step_tile<T, 64, 4>(a, s);
-  return hipErrorInvalidValue;
-}
-
 template <typename T>
 hipError_t launch_outlet_T(const AuxArgs& a, hipStream_t s) {
   const unsigned blocks = (unsigned)((a.geo.plane + 255) / 256);
@@ -820,7 +564,6 @@ hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, lon
 }
 
 #define LBM_INSTANTIATE_STORAGE(T)                                                                                \
-  template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t);                                   \
   template hipError_t launch_outlet_T<T>(const AuxArgs&, hipStream_t);                                            \
   template hipError_t launch_fields_T<T>(const AuxArgs&, int, int, int, int, int, int, double*, hipStream_t);    \
   template hipError_t launch_populations_T<T>(const AuxArgs&, double*, hipStream_t);                              \

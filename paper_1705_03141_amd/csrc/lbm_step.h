@@ -1,0 +1,506 @@
+// lbm_step.h -- the fused step kernel: streaming (as a pull), colour densities, isotropic
+// gradient, MRT collision with enhanced equilibrium, forcing and perturbation, and the
+// recolouring scalars, one pass over HBM per time step (Sec. II).
+//
+// Work decomposition.  A workgroup of TX*TY threads owns a TX x TY column of cells and marches
+// through a chunk of z planes; every thread owns one cell of the column.  The colour gradient
+// of a cell needs the densities of time t of its 26 neighbours, so the 2(TX+2)+2TY cells of
+// the ring around the column are pulled as well (densities only), each by one of the first
+// threads.  Per plane counter p the workgroup
+//   1. loads the scalars (e, psi, w) of source plane p+2 with a 2-cell halo and issues the 27
+//      population loads of the cells of plane p+1 (and of its ring cells) into registers,
+//   2. writes the scalars, decoded into (e, a, b, w), into an LDS ring of 3 planes; barrier,
+//   3. completes the pull of plane p+1 (the population loads have been in flight since 1)
+//      and writes phi and rho of its cells and ring into an LDS ring of 3 planes; barrier,
+//   4. collides plane p with the gradient taken from the density ring, and stores 27
+//      deviations + 5 scalars per cell.
+// The deviations of plane p+1 stay in registers until step 4 of the next plane.
+//
+// Blocks are numbered so that the blocks the hardware sends to one XCD (block ids congruent
+// modulo 8) cover consecutive tiles and z chunks: neighbouring tiles then share one L2 and
+// halo rows are fetched from HBM once.
+#pragma once
+
+#include "lbm_kernels_impl.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------- buffer access
+// The population and scalar planes are read and written with raw buffer instructions: the
+// plane's base is a workgroup-uniform descriptor, the population index j enters as the scalar
+// offset j * plane * sizeof(T), and only the cell's column offset is a per-lane register.
+// This keeps per-lane 64-bit address arithmetic (and its registers) out of the plane loop.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// Raw buffer descriptor over [base, base + bytes); the last word is the GFX9 default format.
+__device__ __forceinline__ rsrc_t buffer_of(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+struct Word;
+template <>
+struct Word<float> {
+  using W = unsigned;
+  static __device__ __forceinline__ W load(rsrc_t r, unsigned vo, int so) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0);
+  }
+  static __device__ __forceinline__ void store(W v, rsrc_t r, unsigned vo, int so) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)vo, so, 0);
+  }
+  static __device__ __forceinline__ float dec(W v) { return __uint_as_float(v); }
+  static __device__ __forceinline__ W enc(float f) { return __float_as_uint(f); }
+};
+template <>
+struct Word<_Float16> {
+  using W = unsigned short;
+  static __device__ __forceinline__ W load(rsrc_t r, unsigned vo, int so) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, so, 0);
+  }
+  static __device__ __forceinline__ void store(W v, rsrc_t r, unsigned vo, int so) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)vo, so, 0);
+  }
+  static __device__ __forceinline__ float dec(W v) { return Codec<_Float16>::dec(__builtin_bit_cast(_Float16, v)); }
+  static __device__ __forceinline__ W enc(float f) { return __builtin_bit_cast(W, Codec<_Float16>::enc(f)); }
+};
+template <>
+struct Word<bf16> {
+  using W = unsigned short;
+  static __device__ __forceinline__ W load(rsrc_t r, unsigned vo, int so) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, so, 0);
+  }
+  static __device__ __forceinline__ void store(W v, rsrc_t r, unsigned vo, int so) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)vo, so, 0);
+  }
+  static __device__ __forceinline__ float dec(W v) { return Codec<bf16>::dec(bf16{v}); }
+  static __device__ __forceinline__ W enc(float f) { return Codec<bf16>::enc(f).bits; }
+};
+
+__device__ __forceinline__ float load_f32(rsrc_t r, unsigned vo, int so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0));
+}
+__device__ __forceinline__ void store_f32(float v, rsrc_t r, unsigned vo, int so) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, so, 0);
+}
+
+// Offsets, in bytes, of the 3 x 3 neighbourhood of column (x, y) within one population plane.
+template <typename T>
+__device__ __forceinline__ void column_offsets(const Geo& G, int x, int y, unsigned (&o)[3][3]) {
+  const int xs[3] = {x == 0 ? G.nx - 1 : x - 1, x, x == G.nx - 1 ? 0 : x + 1};
+  const int ys[3] = {y == 0 ? G.ny - 1 : y - 1, y, y == G.ny - 1 ? 0 : y + 1};
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[b][a] = (unsigned)((ys[b] * G.nx + xs[a]) * (int)sizeof(T));
+}
+
+// Issue the 27 population loads of a pull in mode MODE.  slab[k] covers the 27 population
+// planes of source plane z - 1 + k; the raw word of direction i is left in ld[i].
+template <typename T, int MODE>
+__device__ __forceinline__ void issue_pull(const rsrc_t (&slab)[3], int plane_bytes, const unsigned (&o)[3][3],
+                                           typename Word<T>::W (&ld)[Q]) {
+  static_for<0, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr Src s = resolve<i, MODE>();
+    ld[i] = Word<T>::load(slab[s.dz + 1], o[s.dy + 1][s.dx + 1], s.j * plane_bytes);
+  });
+}
+
+// Single operations the compiler may not fuse with their neighbours into an FMA.
+__device__ __forceinline__ float add_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+__device__ __forceinline__ float sub_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+__device__ __forceinline__ float mul_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ __forceinline__ float div_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a / b;
+}
+
+#ifndef LBM_PULL_GROUP
+#define LBM_PULL_GROUP 3
+#endif
+constexpr int kPullGroup = LBM_PULL_GROUP;
+
+template <typename T, int MODE, bool WANT_DF, int SX>
+__device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], const float4* const (&S)[3], const float2* const (&W)[3],
+                                            int idx0, const PullConst& C, float& rho, float& rho_r, float& rho_b,
+                                            float& e_new, float (&df)[Q], float& shift_out, float& drho_out) {
+  const float4 me = S[1][idx0 + SX + 1];
+  const float e_self = me.x, a_self = me.y, b_self = me.z;
+  const bool track_red = a_self <= b_self;  // the reader's minority colour
+  const float t_self = track_red ? a_self : b_self;
+  const float rho_old = rho_of(C, e_self, a_self);
+  const float E_self = add_nc(C.E0, e_self);
+  const float sgn = track_red ? 1.0f : -1.0f;  // recolouring adds to red, removes from blue
+  const float qE[4] = {0.0f, mul_nc(q_of(1), E_self), mul_nc(q_of(7), E_self), mul_nc(q_of(19), E_self)};
+  const float sq[4] = {0.0f, sgn * qc_of(1), sgn * qc_of(7), sgn * qc_of(19)};
+  // Every operation below is spelled out (fmaf or an *_nc operation) so that the compiler
+  // cannot contract it differently in the cell and ring instances of this function: a cell's
+  // densities are then bitwise the same whichever workgroup pulls it, and results do not
+  // depend on the tiling.
+  float d_rho = Word<T>::dec(ld[0]);
+  float d_t = mul_nc(t_self, d_rho);
+  if constexpr (WANT_DF) df[0] = d_rho;
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr Src s = resolve<i, MODE>();
+    constexpr int off = (s.dy + 1) * SX + s.dx + 1;
+    constexpr int sh = shell_of(i);
+    constexpr bool self_src = s.dx == 0 && s.dy == 0 && s.dz == 0;  // bounce-back
+    const float4 src = S[s.dz + 1][idx0 + off];
+    const float2 w = W[s.dz + 1][idx0 + off];
+    // c_j . w of the source from its non-zero components (a sum started at 0.0f would cost
+    // one more add: 0 + x is not folded because of the sign of zero)
+    const float wy = s.ccy > 0 ? w.x : -w.x, wz = s.ccz > 0 ? w.y : -w.y;
+    float cw = s.ccx != 0 ? (s.ccx > 0 ? src.w : -src.w) : (s.ccy != 0 ? wy : wz);
+    if constexpr (s.ccx != 0 && s.ccy != 0) cw = add_nc(cw, wy);
+    if constexpr ((s.ccx != 0 || s.ccy != 0) && s.ccz != 0) cw = add_nc(cw, wz);
+    float d, inc;
+    if constexpr (self_src) {
+      d = Word<T>::dec(ld[i]);
+      inc = fmaf(sq[sh], cw, mul_nc(t_self, d));
+    } else {
+      d = fmaf(q_of(i), sub_nc(src.x, e_self), Word<T>::dec(ld[i]));
+      const float t = track_red ? src.y : src.z;
+      inc = fmaf(sq[sh], cw, fmaf(qE[sh], sub_nc(t, t_self), mul_nc(t, d)));
+    }
+    d_rho = add_nc(d_rho, d);
+    d_t = add_nc(d_t, inc);
+    if constexpr (WANT_DF) df[i] = d;
+    // issue the LDS reads a few directions at a time: hoisted all at once they take ~150 VGPRs
+    if constexpr (i % kPullGroup == 0) __builtin_amdgcn_sched_barrier(0);
+  });
+  rho = add_nc(rho_old, d_rho);
+  const float rho_t = fmaf(t_self, rho_old, d_t), rho_o = sub_nc(rho, rho_t);
+  rho_r = track_red ? rho_t : rho_o;
+  rho_b = track_red ? rho_o : rho_t;
+  const float d_rhor = track_red ? d_t : sub_nc(d_rho, d_t);
+  const float shift = fmaf(C.dalpha, d_rhor, -mul_nc(1.0f - C.alpha_b, d_rho));  // E(t-1) - E(t)
+  e_new = sub_nc(e_self, shift);
+  shift_out = shift;
+  drho_out = d_rho;
+}
+
+// Call f(std::integral_constant<int, MODE>) for the (workgroup-uniform) pull mode.
+template <typename F>
+__device__ __forceinline__ void with_mode(int mode, F&& f) {
+  switch (mode) {
+    case kLoBB: f(std::integral_constant<int, kLoBB>{}); break;
+    case kLoFS: f(std::integral_constant<int, kLoFS>{}); break;
+    case kHiBB: f(std::integral_constant<int, kHiBB>{}); break;
+    case kHiFS: f(std::integral_constant<int, kHiFS>{}); break;
+    default: f(std::integral_constant<int, kBulk>{}); break;
+  }
+}
+
+// Position of ring cell r (0 <= r < 2(TX+2)+2TY) relative to the column origin.
+template <int TX, int TY>
+__device__ __forceinline__ void ring_cell(int r, int& x, int& y) {
+  if (r < TX + 2) {
+    x = r - 1;
+    y = -1;
+  } else if (r < 2 * (TX + 2)) {
+    x = r - (TX + 2) - 1;
+    y = TY;
+  } else if (r < 2 * (TX + 2) + TY) {
+    x = -1;
+    y = r - 2 * (TX + 2);
+  } else {
+    x = TX;
+    y = r - 2 * (TX + 2) - TY;
+  }
+}
+
+// Pre-collision state of one plane's cell, carried from its pull to its collision.
+struct PlaneState {
+  float df[Q];
+  float rho, rho_r, rho_b, e, shift, drho;
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) df[i] = 0.0f;
+    rho = 1.0f;
+    rho_r = 0.0f;
+    rho_b = 1.0f;
+    e = shift = drho = 0.0f;
+  }
+};
+
+template <typename T, int TX, int TY, bool INIT>
+__global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
+  using Tile = StepTile<TX, TY>;
+  constexpr int NT = Tile::kThreads, NR = Tile::kRing, SX = Tile::SX, NS = Tile::kStaged, DX = Tile::DX,
+                ND = Tile::kDense, KS = Tile::kStagePerThread;
+  __shared__ float4 sS[3][NS];  // staged scalars (e, a, b, w_x) of 3 source planes
+  __shared__ float2 sW[3][NS];  // (w_y, w_z)
+  __shared__ float2 sD[3][ND];  // (phi, rho) of time t of 3 planes, with a 1-cell ring
+
+  const Geo& G = A.geo;
+  const bool zper = G.face_lo == FACE_PERIODIC;
+  const bool outflow = G.face_hi == FACE_OUTFLOW;
+  const int plane = G.plane;
+  const char* gin = static_cast<const char*>(A.g_in);
+  char* gout = static_cast<char*>(A.g_out);
+  const int pb = plane * (int)sizeof(T);                    // bytes of one population plane
+  const unsigned slab_bytes = (unsigned)(Q * pb);           // 27 population planes of one z
+  const unsigned sc_bytes = (unsigned)(5 * plane * 4);      // 5 scalar planes of one z
+
+  // block -> (z chunk, tile); XCD x receives blocks x, x + 8, ...: give it a contiguous range
+  int L = (int)blockIdx.x;
+  const int nb = (int)gridDim.x;
+  if ((nb & 7) == 0) L = (L & 7) * (nb >> 3) + (L >> 3);
+  const int ntiles = A.tiles_x * A.tiles_y;
+  const int chunk = L / ntiles, tile = L - chunk * ntiles;
+  const int tyi = tile / A.tiles_x, txi = tile - tyi * A.tiles_x;
+  const int x0 = txi * TX, y0 = tyi * TY;
+  const int z0 = chunk * A.zchunk, z1 = min(z0 + A.zchunk, G.nz);
+
+  // own cell
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const int gx = wrap(x0 + lx, G.nx), gy = wrap(y0 + ly, G.ny);
+  const bool live = (x0 + lx < G.nx) && (y0 + ly < G.ny);
+  const int col = gy * G.nx + gx;
+  const int sI = (ly + 2) * SX + lx + 2, dI = (ly + 1) * DX + lx + 1;
+  // ring cell
+  const bool ringer = tid < NR;
+  int rx = 0, ry = 0;
+  if (ringer) ring_cell<TX, TY>(tid, rx, ry);
+  const int rgx = wrap(x0 + rx, G.nx), rgy = wrap(y0 + ry, G.ny);
+  const int rcol = rgy * G.nx + rgx;
+  const int sR = (ry + 2) * SX + rx + 2, dR = (ry + 1) * DX + rx + 1;
+  // staged cells
+  unsigned stOff[KS];  // byte offsets in a scalar plane
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int idx = min(tid + k * NT, NS - 1);
+    const int sx = idx % SX, sy = idx / SX;
+    stOff[k] = (unsigned)((wrap(y0 + sy - 2, G.ny) * G.nx + wrap(x0 + sx - 2, G.nx)) * 4);
+  }
+  unsigned oI[3][3], oR[3][3];
+  column_offsets<T>(G, gx, gy, oI);
+  column_offsets<T>(G, rgx, rgy, oR);
+  const unsigned colT = (unsigned)(col * (int)sizeof(T)), col4 = (unsigned)(col * 4);
+
+  auto zsrc = [&](int q) { return zper ? wrap(q, G.nz) : min(max(q, 0), G.nz - 1); };
+  auto needs_pull = [&](int q) { return zper || (q >= 0 && q < G.nz); };
+
+  float st[KS][5];
+  auto stage_load = [&](int q) {
+    const rsrc_t r = buffer_of(A.sc_in + (size_t)zsrc(q) * 5 * (size_t)plane, sc_bytes);
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+      if (k < KS - 1 || tid + k * NT < NS)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) st[k][c] = load_f32(r, stOff[k], c * plane * 4);
+  };
+  auto stage_store = [&](int q) {
+    const int s = slot3(q);
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+      if (k < KS - 1 || tid + k * NT < NS) {
+        const float psi = st[k][1];
+        sS[s][tid + k * NT] = make_float4(st[k][0], psi_a(psi), psi_b(psi), st[k][2]);
+        sW[s][tid + k * NT] = make_float2(st[k][3], st[k][4]);
+      }
+  };
+
+  PlaneState bufA, bufB;
+  bufA.clear();
+  bufB.clear();
+
+  if constexpr (!INIT) {
+    stage_load(z0 - 2);
+    stage_store(z0 - 2);
+    stage_load(z0 - 1);
+    stage_store(z0 - 1);
+  }
+
+  // one pass: pull plane p+1 into nxt, collide plane p from cur
+  auto pass = [&](const int p, PlaneState& cur, PlaneState& nxt) {
+    const int q = p + 1;  // the plane pulled in this pass
+    const bool pull_q = needs_pull(q);
+    const int zq = zper ? wrap(q, G.nz) : q;
+    const bool outlet_q = outflow && zq == G.nz - 1;
+    const bool loads_q = !INIT && pull_q && !outlet_q;
+    const int mode = plane_mode(G, zq);
+
+    // 1. scalars of plane p+2, then the populations of plane p+1
+    if constexpr (!INIT) stage_load(p + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    typename Word<T>::W ldI[Q], ldR[Q];
+    if (loads_q) {
+      const rsrc_t slab[3] = {buffer_of(gin + (size_t)zsrc(q - 1) * slab_bytes, slab_bytes),
+                              buffer_of(gin + (size_t)zq * slab_bytes, slab_bytes),
+                              buffer_of(gin + (size_t)zsrc(q + 1) * slab_bytes, slab_bytes)};
+      with_mode(mode, [&](auto M) {
+        if (ringer) issue_pull<T, decltype(M)::value>(slab, pb, oR, ldR);
+        issue_pull<T, decltype(M)::value>(slab, pb, oI, ldI);
+      });
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // 2. staged scalars to LDS
+    if constexpr (!INIT) stage_store(p + 2);
+    __syncthreads();
+
+    // 3. complete the pull of plane q: own cell (with deviations) and ring cell (densities).
+    // The LDS bases are made opaque per pass so that the compiler does not hoist one address
+    // per neighbour out of the plane loop.
+    int bI = sI - SX - 1, bR = sR - SX - 1;
+    asm volatile("" : "+v"(bI), "+v"(bR));
+    if (!pull_q) nxt.clear();
+    if (pull_q) {
+      const int s = slot3(q);
+      const float4* S[3] = {sS[slot3(q - 1)], sS[s], sS[slot3(q + 1)]};
+      const float2* W[3] = {sW[slot3(q - 1)], sW[s], sW[slot3(q + 1)]};
+      // the ring first: its loads are the older ones and its registers are freed sooner
+      if (ringer) {
+        float r_rho, r_r, r_b, r_e, r_sh, r_dr, r_df[Q];
+        if constexpr (INIT) {
+          init_cell<false>(A.init, A.pc, G.n, (long long)zq * plane + rcol, r_rho, r_r, r_b, r_e, r_df);
+        } else if (outlet_q) {
+          outlet_cell<false>(A.outlet, A.pc, plane, rcol, r_rho, r_r, r_b, r_e, r_df);
+        } else {
+          with_mode(mode, [&](auto M) {
+            finish_pull<T, decltype(M)::value, false, SX>(ldR, S, W, bR, A.pc, r_rho, r_r, r_b, r_e, r_df, r_sh, r_dr);
+          });
+        }
+        if (is_inflow(G, rgx, rgy, zq)) {
+          r_rho = G.rho_r0;
+          r_r = G.rho_r0;
+          r_b = 0.0f;
+        }
+        sD[s][dR] = make_float2((r_r - r_b) / r_rho, r_rho);
+      }
+      if constexpr (INIT) {
+        init_cell<true>(A.init, A.pc, G.n, (long long)zq * plane + col, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e, nxt.df);
+        nxt.shift = nxt.drho = 0.0f;
+      } else if (outlet_q) {
+        outlet_cell<true>(A.outlet, A.pc, plane, col, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e, nxt.df);
+        nxt.shift = nxt.drho = 0.0f;
+      } else {
+        with_mode(mode, [&](auto M) {
+          finish_pull<T, decltype(M)::value, true, SX>(ldI, S, W, bI, A.pc, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e,
+                                                       nxt.df, nxt.shift, nxt.drho);
+        });
+      }
+      if (is_inflow(G, gx, gy, zq)) {  // R10: inflow sites are pure red at rho_r0
+        nxt.rho = G.rho_r0;
+        nxt.rho_r = G.rho_r0;
+        nxt.rho_b = 0.0f;
+      }
+      sD[s][dI] = make_float2((nxt.rho_r - nxt.rho_b) / nxt.rho, nxt.rho);
+    }
+    __syncthreads();
+
+    // 4. collide plane p
+    if (p >= z0 && live) {
+      const size_t cell = (size_t)p * plane + col;
+      const rsrc_t gslab = buffer_of(gout + (size_t)p * slab_bytes, slab_bytes);
+      const rsrc_t sslab = buffer_of(A.sc_out + (size_t)p * 5 * (size_t)plane, sc_bytes);
+      if (is_inflow(G, gx, gy, p)) {
+        // inflow site: emit the red equilibrium at rho_r0, u_in e_z (R10)
+        const float u = inflow_speed(G, (long long)cell, A.step);
+        static_for<0, Q>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          Word<T>::store(Word<T>::enc(eq_dev<i>(G.rho_r0, 0.0f, 0.0f, u)), gslab, colT, i * pb);
+        });
+        store_f32(0.0f, sslab, col4, 0);              // rho_r0 (1 - alpha_r) = E0 exactly
+        store_f32(-0.0f, sslab, col4, plane * 4);     // pure red
+        store_f32(0.0f, sslab, col4, 2 * plane * 4);
+        store_f32(0.0f, sslab, col4, 3 * plane * 4);
+        store_f32(0.0f, sslab, col4, 4 * plane * 4);
+      } else {
+        const int sm = (!zper && p == 0) ? slot3(p) : slot3(p - 1);
+        const int sp = (!zper && p == G.nz - 1) ? slot3(p) : slot3(p + 1);
+        const int s0 = slot3(p);
+        float gp[3], gr[3];
+        {
+          float vp[3][3][3], vr[3][3][3];
+          int b0 = dI - DX - 1;
+          asm volatile("" : "+v"(b0));
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+              const int o = b0 + dy * DX + dx;
+              const float2 a = sD[sm][o], b = sD[s0][o], c = sD[sp][o];
+              vp[0][dy][dx] = a.x;
+              vr[0][dy][dx] = a.y;
+              vp[1][dy][dx] = b.x;
+              vr[1][dy][dx] = b.y;
+              vp[2][dy][dx] = c.x;
+              vr[2][dy][dx] = c.y;
+            }
+          gradient27(vp, gp);
+          gradient27(vr, gr);
+        }
+        CellOut o;
+        collide_cell(A.cp, A.rates, cur.df, cur.shift, cur.drho, cur.rho, cur.rho_r, cur.rho_b, gp, gr, o);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Word<T>::store(Word<T>::enc(o.g[i]), gslab, colT, i * pb);
+        store_f32(cur.e, sslab, col4, 0);
+        store_f32(psi_encode(cur.rho_r, cur.rho_b, cur.rho), sslab, col4, plane * 4);
+        store_f32(o.wx, sslab, col4, 2 * plane * 4);
+        store_f32(o.wy, sslab, col4, 3 * plane * 4);
+        store_f32(o.wz, sslab, col4, 4 * plane * 4);
+      }
+    }
+  };
+
+  // unrolled by two so that the two plane states swap roles instead of being copied
+  for (int p = z0 - 2; p < z1; p += 2) {
+    pass(p, bufA, bufB);
+    if (p + 1 < z1) pass(p + 1, bufB, bufA);
+  }
+}
+
+// ================================================================== launchers
+template <typename T, int TX, int TY>
+hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
+  const long long blocks = (long long)a.tiles_x * a.tiles_y * a.nchunks;
+  if (a.init_mode)
+    hipLaunchKernelGGL((step_kernel<T, TX, TY, true>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
+  else
+    hipLaunchKernelGGL((step_kernel<T, TX, TY, false>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int TX, int TY>
+int resident_tile(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)step_kernel<T, TX, TY, false>, TX * TY, 0) !=
+      hipSuccess)
+    return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+template <typename T>
+hipError_t launch_step_T(const StepArgs& a, int tx, int ty, hipStream_t s) {
+  if (tx == 32 && ty == 4) return launch_step_tile<T, 32, 4>(a, s);
+  if (tx == 32 && ty == 8) return launch_step_tile<T, 32, 8>(a, s);
+  if (tx == 64 && ty == 4) return launch_step_tile<T, 64, 4>(a, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+int step_resident_blocks_T(int tx, int ty, int device) {
+  if (tx == 32 && ty == 4) return resident_tile<T, 32, 4>(device);
+  if (tx == 32 && ty == 8) return resident_tile<T, 32, 8>(device);
+  if (tx == 64 && ty == 4) return resident_tile<T, 64, 4>(device);
+  return 0;
+}
+
+#define LBM_INSTANTIATE_STEP(T)                                                 \
+  template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t); \
+  template int step_resident_blocks_T<T>(int, int, int);
+
+}  // namespace lbm

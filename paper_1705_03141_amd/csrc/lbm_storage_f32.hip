@@ -1,6 +1,7 @@
 // lbm_storage_f32.hip -- kernels instantiated for float population storage.
-#include "lbm_kernels_impl.h"
+#include "lbm_step.h"
 
 namespace lbm {
 LBM_INSTANTIATE_STORAGE(float)
+LBM_INSTANTIATE_STEP(float)
 }  // namespace lbm
