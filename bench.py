@@ -33,9 +33,10 @@ PEAK_GBS = 8000.0
 # HBM bytes per step-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
 # scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000); valid
 # only for the kernel sources they were taken on.
-COUNTERS = {"sources_sha16": "bdb5ef059caae684", "storage": "f32", "fetch_kib": 1573536.0, "fetch_scale": 2.0,
-            "write_kib": 1077248.0, "write_scale": 1.0}
-KERNEL_SOURCES = ["lbm_cell.h", "lbm_device.h", "lbm_kernels.h", "lbm_kernels_impl.h", "lbm_storage_f32.hip"]
+COUNTERS = {"sources_sha16": "38ab0bbf8b073e16", "storage": "f32", "fetch_kib": 567604.0, "fetch_scale": 2.0,
+            "write_kib": 1048576.0, "write_scale": 1.0}
+KERNEL_SOURCES = ["csrc/lbm_cell.h", "csrc/lbm_device.h", "csrc/lbm_kernels.h", "csrc/lbm_kernels_impl.h",
+                  "csrc/lbm_step.h", "csrc/lbm_storage_f32.hip", "build.py"]
 STD_BYTES = 432.0  # 2 colours x 27 populations x 4 B, read + write
 
 
@@ -68,7 +69,7 @@ def kernel_sources_sha16() -> str:
 
     h = hashlib.sha256()
     for fn in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "paper_1705_03141_amd", "csrc", fn), "rb") as f:
+        with open(os.path.join(HERE, "paper_1705_03141_amd", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
