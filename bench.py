@@ -123,6 +123,33 @@ def copy_calibration(nbytes=1 << 30, reps=5):
                       "GBps_read_plus_write": 2 * nbytes / ms / 1e6}), flush=True)
 
 
+def interface_error(workload: str, steps: int):
+    """Interface-position error of FP16 / BF16 storage against FP32 storage after `steps`
+    steps (metrics.interface_position_error; lattice units)."""
+    from paper_1705_03141_amd import lbm, metrics
+    from paper_1705_03141_amd import workloads as W
+
+    pb = W.cfg_rayleigh_taylor() if workload == "rt" else W.cfg_jet()
+    phi = {}
+    for st in ("f32", "f16", "bf16"):
+        lat = lbm.Lattice(pb, storage=st)
+        done = 0
+        while done < steps:
+            k = min(2000, steps - done)
+            lat.step(k)
+            lat.sync()
+            done += k
+            log(f"{pb.name} {st}: {done}/{steps} steps")
+        phi[st] = lat.field("phi")
+        if lat.diagnostics()["unstable"]:
+            log(f"{pb.name} {st}: unstable")
+        lat.close()
+    out = {"workload": pb.name, "steps": steps}
+    for st in ("f16", "bf16"):
+        out[st] = metrics.interface_position_error(phi[st], phi["f32"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +160,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--interface-error", choices=["rt", "jet"],
+                    help="instead of timing: run the workload for --steps steps with FP32, FP16 and BF16 "
+                         "storage and print the interface-position error of the half-precision runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -141,6 +171,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.interface_error:
+        interface_error(args.interface_error, args.steps)
         return
 
     from paper_1705_03141_amd import workloads as W

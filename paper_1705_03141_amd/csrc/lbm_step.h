@@ -11,7 +11,8 @@
 //      population loads of the cells of plane p+1 (and of its ring cells) into registers,
 //   2. writes the scalars, decoded into (e, a, b, w), into an LDS ring of 3 planes; barrier,
 //   3. completes the pull of plane p+1 (the population loads have been in flight since 1)
-//      and writes phi and rho of its cells and ring into an LDS ring of 3 planes; barrier,
+//      and writes rho_r/rho, rho_b/rho and rho of its cells and ring into an LDS ring of 3
+//      planes; barrier,
 //   4. collides plane p with the gradient taken from the density ring, and stores 27
 //      deviations + 5 scalars per cell.
 // The deviations of plane p+1 stay in registers until step 4 of the next plane.
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
                 ND = Tile::kDense, KS = Tile::kStagePerThread;
   __shared__ float4 sS[3][NS];  // staged scalars (e, a, b, w_x) of 3 source planes
   __shared__ float2 sW[3][NS];  // (w_y, w_z)
-  __shared__ float2 sD[3][ND];  // (phi, rho) of time t of 3 planes, with a 1-cell ring
+  __shared__ float4 sD[3][ND];  // (rho_r/rho, rho_b/rho, rho) of time t of 3 planes, 1-cell ring
 
   const Geo& G = A.geo;
   const bool zper = G.face_lo == FACE_PERIODIC;
@@ -377,7 +378,7 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
           r_r = G.rho_r0;
           r_b = 0.0f;
         }
-        sD[s][dR] = make_float2((r_r - r_b) / r_rho, r_rho);
+        sD[s][dR] = make_float4(r_r / r_rho, r_b / r_rho, r_rho, 0.0f);
       }
       if constexpr (INIT) {
         init_cell<true>(A.init, A.pc, G.n, (long long)zq * plane + col, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e, nxt.df);
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
         nxt.rho_r = G.rho_r0;
         nxt.rho_b = 0.0f;
       }
-      sD[s][dI] = make_float2((nxt.rho_r - nxt.rho_b) / nxt.rho, nxt.rho);
+      sD[s][dI] = make_float4(nxt.rho_r / nxt.rho, nxt.rho_b / nxt.rho, nxt.rho, 0.0f);
     }
     __syncthreads();
 
@@ -421,6 +422,11 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
         const int sm = (!zper && p == 0) ? slot3(p) : slot3(p - 1);
         const int sp = (!zper && p == G.nz - 1) ? slot3(p) : slot3(p + 1);
         const int s0 = slot3(p);
+        // grad phi from the cell's minority colour fraction t (phi = 2a - 1 = 1 - 2b): near a
+        // pure phase phi = -1 + 2a carries only the absolute precision of 1 in FP32, while a
+        // itself keeps its relative precision, so the direction of grad phi stays defined
+        // wherever the fields define it.
+        const bool red_minor = cur.rho_r <= cur.rho_b;
         float gp[3], gr[3];
         {
           float vp[3][3][3], vr[3][3][3];
@@ -431,16 +437,20 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
               const int o = b0 + dy * DX + dx;
-              const float2 a = sD[sm][o], b = sD[s0][o], c = sD[sp][o];
-              vp[0][dy][dx] = a.x;
-              vr[0][dy][dx] = a.y;
-              vp[1][dy][dx] = b.x;
-              vr[1][dy][dx] = b.y;
-              vp[2][dy][dx] = c.x;
-              vr[2][dy][dx] = c.y;
+              const float4 a = sD[sm][o], b = sD[s0][o], c = sD[sp][o];
+              vp[0][dy][dx] = red_minor ? a.x : a.y;
+              vr[0][dy][dx] = a.z;
+              vp[1][dy][dx] = red_minor ? b.x : b.y;
+              vr[1][dy][dx] = b.z;
+              vp[2][dy][dx] = red_minor ? c.x : c.y;
+              vr[2][dy][dx] = c.z;
             }
           gradient27(vp, gp);
           gradient27(vr, gr);
+          const float two = red_minor ? 2.0f : -2.0f;
+          gp[0] *= two;
+          gp[1] *= two;
+          gp[2] *= two;
         }
         CellOut o;
         collide_cell(A.cp, A.rates, cur.df, cur.shift, cur.drho, cur.rho, cur.rho_r, cur.rho_b, gp, gr, o);

@@ -1,0 +1,48 @@
+"""Host-side measures on read-back fields (numpy, no GPU).
+
+interface_position_error(phi_a, phi_b): how far apart two runs put the interface.  Over the
+cells where run b sees the interface (|phi_b| < 0.9), the local displacement of the phase
+field is |phi_a - phi_b| / |grad phi_b| in lattice units (phi changes by |grad phi| per lattice
+unit across the interface, so a shift of the interface by d moves phi by d |grad phi|).
+Returns the mean and the maximum over those cells.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def interface_position_error(phi_a: np.ndarray, phi_b: np.ndarray, band: float = 0.9, periodic=(True, True, False),
+                             min_grad: float = 1e-3) -> dict:
+    """Interface displacement of field a relative to field b (arrays indexed [z, y, x]).
+
+    periodic: per axis (x, y, z) whether central differences wrap.  Cells whose phase
+    gradient is below min_grad (flat plateaus inside the band) are skipped."""
+    if phi_a.shape != phi_b.shape:
+        raise ValueError("fields differ in shape")
+    grads = []
+    for axis_xyz, per in zip((2, 1, 0), periodic):
+        if per:
+            d = 0.5 * (np.roll(phi_b, -1, axis=axis_xyz) - np.roll(phi_b, 1, axis=axis_xyz))
+        else:
+            d = np.gradient(phi_b, axis=axis_xyz)
+        grads.append(d)
+    gmag = np.sqrt(sum(g * g for g in grads))
+    sel = (np.abs(phi_b) < band) & (gmag > min_grad)
+    if not np.any(sel):
+        return {"cells": 0, "mean_lu": 0.0, "max_lu": 0.0}
+    disp = np.abs(phi_a[sel] - phi_b[sel]) / gmag[sel]
+    return {"cells": int(sel.sum()), "mean_lu": float(disp.mean()), "max_lu": float(disp.max())}
+
+
+def relative_errors(got: dict, ref: dict) -> dict:
+    """Parity measures of two field sets: e_rho = max|rho_a - rho_b| / max|rho_b| (also per
+    colour, on the same scale), e_u = max|u_a - u_b| / max|u_b|."""
+    rho_ref = ref["rho_r"] + ref["rho_b"]
+    scale = float(np.abs(rho_ref).max())
+    e = {k: float(np.abs(got[k] - ref[k]).max() / scale) for k in ("rho_r", "rho_b")}
+    e["rho"] = float(np.abs(got["rho_r"] + got["rho_b"] - rho_ref).max() / scale)
+    umag = float(np.abs(ref["u"]).max())
+    du = float(np.abs(got["u"] - ref["u"]).max())
+    e["u"] = du / umag if umag > 0 else du
+    e["umax_ref"] = umag
+    return e
