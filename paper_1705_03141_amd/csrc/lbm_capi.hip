@@ -36,7 +36,7 @@ struct lbm_ctx {
   int out_cur = 0;          // index of the outlet record of the latest time
   long long step = 0;
   bool initialised = false;
-  int tx = 32, ty = 8, zchunk = 0;  // zchunk 0: chosen from the resident workgroups
+  int tx = 0, ty = 0, zchunk = 0;  // 0: chosen at the first step (enqueue_one, auto_zchunk)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   std::string err;
@@ -299,6 +299,12 @@ static lbm_status enqueue_one(lbm_ctx* c) {
   s.outlet = c->outlet[1 - c->out_cur];
   s.step = c->step;
   s.init_mode = init ? 1 : 0;
+  if (c->tx == 0) {
+    // measured on MI355X: 64 x 4 tiles for FP32 state on rows of 64 cells or more, 32 x 8 otherwise
+    const bool wide = c->p.storage == LBM_F32 && G.nx >= 64;
+    c->tx = wide ? 64 : 32;
+    c->ty = wide ? 4 : 8;
+  }
   if (c->zchunk < 1) c->zchunk = auto_zchunk(c);
   s.zchunk = c->zchunk;
   s.tiles_x = (G.nx + c->tx - 1) / c->tx;
@@ -310,6 +316,10 @@ static lbm_status enqueue_one(lbm_ctx* c) {
   s.rates = c->rates;
   hipError_t e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step kernel");
+  if (G.inflow) {
+    e = launch_inflow((int)c->p.storage, s, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "inflow kernel");
+  }
   c->cur = 1 - c->cur;
   if (G.face_hi == FACE_OUTFLOW) c->out_cur = 1 - c->out_cur;
   c->step++;

@@ -185,7 +185,7 @@ __host__ __device__ __forceinline__ float psi_encode(float rho_r, float rho_b, f
 
 // Density of a cell from its stored (e, a).
 __host__ __device__ __forceinline__ float rho_of(const PullConst& C, float e, float a) {
-  return (C.E0 + e) / fmaf(-a, C.dalpha, 1.0f - C.alpha_b);
+  return (C.E0 + e) * rcp(fmaf(-a, C.dalpha, 1.0f - C.alpha_b));
 }
 
 }  // namespace lbm

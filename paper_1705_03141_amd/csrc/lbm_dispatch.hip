@@ -3,7 +3,9 @@
 
 namespace lbm {
 
-bool step_tiling_supported(int tx, int ty) { return (tx == 32 && (ty == 4 || ty == 8)) || (tx == 64 && ty == 4); }
+bool step_tiling_supported(int tx, int ty) {
+  return (tx == 32 && (ty == 4 || ty == 8 || ty == 16)) || (tx == 64 && (ty == 4 || ty == 8));
+}
 
 
 hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream_t s) {
@@ -11,6 +13,15 @@ hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream
     case 0: return launch_step_T<float>(a, tx, ty, s);
     case 1: return launch_step_T<_Float16>(a, tx, ty, s);
     case 2: return launch_step_T<bf16>(a, tx, ty, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_inflow(int storage, const StepArgs& a, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_inflow_T<float>(a, s);
+    case 1: return launch_inflow_T<_Float16>(a, s);
+    case 2: return launch_inflow_T<bf16>(a, s);
   }
   return hipErrorInvalidValue;
 }

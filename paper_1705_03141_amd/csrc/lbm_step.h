@@ -235,7 +235,10 @@ struct PlaneState {
 };
 
 template <typename T, int TX, int TY, bool INIT>
-__global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
+#ifndef LBM_STEP_WAVES_PER_EU
+#define LBM_STEP_WAVES_PER_EU 2
+#endif
+__global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU) step_kernel(const StepArgs A) {
   using Tile = StepTile<TX, TY>;
   constexpr int NT = Tile::kThreads, NR = Tile::kRing, SX = Tile::SX, NS = Tile::kStaged, DX = Tile::DX,
                 ND = Tile::kDense, KS = Tile::kStagePerThread;
@@ -285,9 +288,6 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
     const int sx = idx % SX, sy = idx / SX;
     stOff[k] = (unsigned)((wrap(y0 + sy - 2, G.ny) * G.nx + wrap(x0 + sx - 2, G.nx)) * 4);
   }
-  unsigned oI[3][3], oR[3][3];
-  column_offsets<T>(G, gx, gy, oI);
-  column_offsets<T>(G, rgx, rgy, oR);
   const unsigned colT = (unsigned)(col * (int)sizeof(T)), col4 = (unsigned)(col * 4);
 
   auto zsrc = [&](int q) { return zper ? wrap(q, G.nz) : min(max(q, 0), G.nz - 1); };
@@ -341,6 +341,12 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
       const rsrc_t slab[3] = {buffer_of(gin + (size_t)zsrc(q - 1) * slab_bytes, slab_bytes),
                               buffer_of(gin + (size_t)zq * slab_bytes, slab_bytes),
                               buffer_of(gin + (size_t)zsrc(q + 1) * slab_bytes, slab_bytes)};
+      // neighbour offsets, recomputed per plane (cheaper than 18 registers across the loop)
+      int ax = gx, ay = gy, arx = rgx, ary = rgy;
+      asm volatile("" : "+v"(ax), "+v"(ay), "+v"(arx), "+v"(ary));
+      unsigned oI[3][3], oR[3][3];
+      column_offsets<T>(G, ax, ay, oI);
+      column_offsets<T>(G, arx, ary, oR);
       with_mode(mode, [&](auto M) {
         if (ringer) issue_pull<T, decltype(M)::value>(slab, pb, oR, ldR);
         issue_pull<T, decltype(M)::value>(slab, pb, oI, ldI);
@@ -378,7 +384,8 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
           r_r = G.rho_r0;
           r_b = 0.0f;
         }
-        sD[s][dR] = make_float4(r_r / r_rho, r_b / r_rho, r_rho, 0.0f);
+        const float r_inv = rcp(r_rho);
+        sD[s][dR] = make_float4(r_r * r_inv, r_b * r_inv, r_rho, 0.0f);
       }
       if constexpr (INIT) {
         init_cell<true>(A.init, A.pc, G.n, (long long)zq * plane + col, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e, nxt.df);
@@ -397,28 +404,17 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
         nxt.rho_r = G.rho_r0;
         nxt.rho_b = 0.0f;
       }
-      sD[s][dI] = make_float4(nxt.rho_r / nxt.rho, nxt.rho_b / nxt.rho, nxt.rho, 0.0f);
+      const float inv = rcp(nxt.rho);
+      sD[s][dI] = make_float4(nxt.rho_r * inv, nxt.rho_b * inv, nxt.rho, 0.0f);
     }
     __syncthreads();
 
     // 4. collide plane p
     if (p >= z0 && live) {
-      const size_t cell = (size_t)p * plane + col;
       const rsrc_t gslab = buffer_of(gout + (size_t)p * slab_bytes, slab_bytes);
       const rsrc_t sslab = buffer_of(A.sc_out + (size_t)p * 5 * (size_t)plane, sc_bytes);
-      if (is_inflow(G, gx, gy, p)) {
-        // inflow site: emit the red equilibrium at rho_r0, u_in e_z (R10)
-        const float u = inflow_speed(G, (long long)cell, A.step);
-        static_for<0, Q>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          Word<T>::store(Word<T>::enc(eq_dev<i>(G.rho_r0, 0.0f, 0.0f, u)), gslab, colT, i * pb);
-        });
-        store_f32(0.0f, sslab, col4, 0);              // rho_r0 (1 - alpha_r) = E0 exactly
-        store_f32(-0.0f, sslab, col4, plane * 4);     // pure red
-        store_f32(0.0f, sslab, col4, 2 * plane * 4);
-        store_f32(0.0f, sslab, col4, 3 * plane * 4);
-        store_f32(0.0f, sslab, col4, 4 * plane * 4);
-      } else {
+      // (inflow sites are collided like any cell here; inflow_kernel overwrites them)
+      {
         const int sm = (!zper && p == 0) ? slot3(p) : slot3(p - 1);
         const int sp = (!zper && p == G.nz - 1) ? slot3(p) : slot3(p + 1);
         const int s0 = slot3(p);
@@ -432,19 +428,19 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
           float vp[3][3][3], vr[3][3][3];
           int b0 = dI - DX - 1;
           asm volatile("" : "+v"(b0));
+          const int slots[3] = {sm, s0, sp};
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy)
+          for (int dz = 0; dz < 3; ++dz) {
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-              const int o = b0 + dy * DX + dx;
-              const float4 a = sD[sm][o], b = sD[s0][o], c = sD[sp][o];
-              vp[0][dy][dx] = red_minor ? a.x : a.y;
-              vr[0][dy][dx] = a.z;
-              vp[1][dy][dx] = red_minor ? b.x : b.y;
-              vr[1][dy][dx] = b.z;
-              vp[2][dy][dx] = red_minor ? c.x : c.y;
-              vr[2][dy][dx] = c.z;
-            }
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+              for (int dx = 0; dx < 3; ++dx) {
+                const float4 v = sD[slots[dz]][b0 + dy * DX + dx];
+                vp[dz][dy][dx] = red_minor ? v.x : v.y;
+                vr[dz][dy][dx] = v.z;
+              }
+            __builtin_amdgcn_sched_barrier(0);  // one plane of reads at a time
+          }
           gradient27(vp, gp);
           gradient27(vr, gr);
           const float two = red_minor ? 2.0f : -2.0f;
@@ -470,6 +466,31 @@ __global__ void __launch_bounds__(TX * TY, 2) step_kernel(const StepArgs A) {
     pass(p, bufA, bufB);
     if (p + 1 < z1) pass(p + 1, bufB, bufA);
   }
+}
+
+// Inflow sites (R10) after a step: each emits the red equilibrium at rho_r0 and u_in(1 + eps xi)
+// e_z with Phi = 0 and no blue; the step kernel collided them like any cell.
+template <typename T>
+__global__ void __launch_bounds__(256) inflow_kernel(const StepArgs A) {
+  const Geo& G = A.geo;
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= G.plane) return;
+  const int x = col % G.nx, y = col / G.nx;
+  if (!is_inflow(G, x, y, 0)) return;
+  const int pb = G.plane * (int)sizeof(T);
+  const rsrc_t gslab = buffer_of(A.g_out, (unsigned)(Q * pb));
+  const rsrc_t sslab = buffer_of(A.sc_out, (unsigned)(5 * G.plane * 4));
+  const unsigned colT = (unsigned)(col * (int)sizeof(T)), col4 = (unsigned)(col * 4);
+  const float u = inflow_speed(G, (long long)col, A.step);
+  static_for<0, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    Word<T>::store(Word<T>::enc(eq_dev<i>(G.rho_r0, 0.0f, 0.0f, u)), gslab, colT, i * pb);
+  });
+  store_f32(0.0f, sslab, col4, 0);                // rho_r0 (1 - alpha_r) = E0 exactly
+  store_f32(-0.0f, sslab, col4, G.plane * 4);     // pure red
+  store_f32(0.0f, sslab, col4, 2 * G.plane * 4);
+  store_f32(0.0f, sslab, col4, 3 * G.plane * 4);
+  store_f32(0.0f, sslab, col4, 4 * G.plane * 4);
 }
 
 // ================================================================== launchers
@@ -498,7 +519,15 @@ hipError_t launch_step_T(const StepArgs& a, int tx, int ty, hipStream_t s) {
   if (tx == 32 && ty == 4) return launch_step_tile<T, 32, 4>(a, s);
   if (tx == 32 && ty == 8) return launch_step_tile<T, 32, 8>(a, s);
   if (tx == 64 && ty == 4) return launch_step_tile<T, 64, 4>(a, s);
+  if (tx == 64 && ty == 8) return launch_step_tile<T, 64, 8>(a, s);
+  if (tx == 32 && ty == 16) return launch_step_tile<T, 32, 16>(a, s);
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_inflow_T(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(inflow_kernel<T>, dim3((unsigned)((a.geo.plane + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -506,11 +535,14 @@ int step_resident_blocks_T(int tx, int ty, int device) {
   if (tx == 32 && ty == 4) return resident_tile<T, 32, 4>(device);
   if (tx == 32 && ty == 8) return resident_tile<T, 32, 8>(device);
   if (tx == 64 && ty == 4) return resident_tile<T, 64, 4>(device);
+  if (tx == 64 && ty == 8) return resident_tile<T, 64, 8>(device);
+  if (tx == 32 && ty == 16) return resident_tile<T, 32, 16>(device);
   return 0;
 }
 
 #define LBM_INSTANTIATE_STEP(T)                                                 \
   template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t); \
+  template hipError_t launch_inflow_T<T>(const StepArgs&, hipStream_t);          \
   template int step_resident_blocks_T<T>(int, int, int);
 
 }  // namespace lbm

@@ -1,0 +1,162 @@
+"""Flow-level pins of the FP64 oracle (CPU): closed forms and invariants of whole runs that a
+mistake in the equilibrium, the viscosity interpolation, the wall rules, the inflow or the
+surface-tension dynamics would break.
+
+* oscillating droplet: the n = 2 period against Lamb's frequency with the viscous
+  correction of Miller & Scriven (Sec. III B, Eqs. (resoFreq), (Lamb)), on the paper's
+  41^3 prolate droplet (Table II, first row);
+* free-slip walls exert no friction: a body-force-driven channel between them accelerates
+  as one block;
+* inflow + convective outflow: a uniform plug flow of the inflow state is a fixed point;
+* two-layer Couette-Poiseuille flow with nu_r != nu_b: the steady profile is the piecewise
+  parabola with continuous velocity and shear stress (the viscous stress the enhanced
+  equilibrium's Phi term is there to get right, Sec. II).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1705_03141_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def _extremum_time(t, v, k, kind):
+    """Time of the extremum at sample k by a parabola through its neighbours."""
+    y0, y1, y2 = v[k - 1], v[k], v[k + 1]
+    den = y0 - 2 * y1 + y2
+    off = 0.5 * (y0 - y2) / den if den != 0 else 0.0
+    return t[k] + off * (t[1] - t[0])
+
+
+def test_lamb_oscillation_period(O):
+    """41^3, prolate spheroid with semi-axes 15, 11, 11 at the centre, density ratio 4
+    (droplet rho = 1 in rho = 0.25, reading R19), nu = 3.333e-3 in both, A = 1e-2, Suga's
+    rates (Table II, first row).  The x extent starts at its maximum; twice the time to its
+    first minimum is compared with T = 2 pi / omega_2 of Eqs. (resoFreq), (Lamb).
+
+    Loose pin: this oracle's period comes out ~24 % longer than the formula here, ~15 % for
+    the same droplet scaled by 1.5 on 61^3, and ~13 % at density ratio 1: the gap shrinks
+    with resolution, while the paper reports 0.6 % at 41^3 with set-up details (box walls,
+    interface width, definition of R_e) that it does not give.  30 % still fails a surface
+    tension off by a factor 2 or a wrong sign in the perturbation."""
+    nu, A = 3.333e-3, 1.0e-2
+    rho1, rho2 = 1.0, 0.25
+    pb = W.static_droplet(n=41, rho_r0=rho1, rho_b0=rho2, nu=nu, A=A, beta=0.7, semi_axes=(15.0, 11.0, 11.0))
+    pb.s = None
+    o = O.Oracle(pb)
+    tau = 3.0 * nu + 0.5
+    sigma = 4.0 / 9.0 * A * tau
+    Re = (15.0 * 11.0 * 11.0) ** (1.0 / 3.0)
+    n = 2
+    w_star = math.sqrt(n * (n + 1) * (n - 1) * (n + 2) * sigma / (Re ** 3 * (n * rho2 + (n + 1) * rho1)))
+    mu1, mu2 = rho1 * nu, rho2 * nu
+    chi = ((2 * n + 1) ** 2 * math.sqrt(mu1 * mu2 * rho1 * rho2)
+           / (math.sqrt(2.0) * Re * (n * rho2 + (n + 1) * rho1) * (math.sqrt(mu1 * rho1) + math.sqrt(mu2 * rho2))))
+    omega = w_star - 0.5 * chi * math.sqrt(w_star) + 0.25 * chi * chi
+    T_th = 2 * math.pi / omega
+    # half-length of the droplet along x through its centre: where phi crosses 0
+    c = 20
+    every, total = 25, int(0.75 * T_th)
+    ts, ext = [], []
+    for step in range(0, total + 1, every):
+        if step:
+            o.step(every)
+        phi = o.fields()["phi"][c, c, :]
+        k = c
+        while k + 1 < pb.nx and phi[k + 1] > 0:
+            k += 1
+        ts.append(step)
+        ext.append(k + phi[k] / (phi[k] - phi[k + 1]) - c)
+    ts, ext = np.array(ts, float), np.array(ext)
+    kmin = int(np.argmin(ext))
+    assert 0 < kmin < len(ext) - 1, "no minimum of the x extent"
+    t_min = _extremum_time(ts, ext, kmin, "min")
+    T_sim = 2.0 * t_min
+    err = abs(T_sim - T_th) / T_th
+    print(f"T_th {T_th:.1f}  T_sim {T_sim:.1f}  error {100 * err:.1f} %")
+    assert err < 0.30, (T_sim, T_th)
+
+
+def test_free_slip_channel_has_no_wall_friction(O):
+    """Single-phase fluid between free-slip walls at both z faces, pushed along x by a
+    uniform force: every plane accelerates alike, u_x = g t exactly (with the F/2 of the
+    velocity definition: u_x(t) = g (t + 1/2) after t steps from rest)."""
+    H, g = 12, 1e-5
+    shape = (H, 2, 2)
+    pb = W.Problem(name="slip", nx=2, ny=2, nz=H, rho_r0=1.0, rho_b0=1.0, nu_r=0.05, nu_b=0.05, A=0.0, beta=0.7,
+                   faces=(W.PERIODIC,) * 4 + (W.FREESLIP,) * 2, force_model=1, g=(g, 0.0, 0.0), rho_ref=0.0,
+                   rho_r=np.ones(shape), rho_b=np.zeros(shape), u=np.zeros((3,) + shape))
+    o = O.Oracle(pb)
+    steps = 200
+    o.step(steps)
+    f = o.fields()
+    ux = f["u"][0]
+    assert np.abs(ux - g * (steps + 0.5)).max() < 1e-12 * steps
+    assert np.abs(f["u"][1:]).max() < 1e-14
+
+
+def test_inflow_and_outflow_keep_a_uniform_plug_flow(O):
+    """The whole z = 0 plane is inflow and the top is a convective outlet; the lattice starts
+    in the inflow state (red at rho_r0, u = u_in e_z).  That state is a fixed point of the
+    bulk step, of the inflow rule (R10) and of the outflow rule (R11)."""
+    nx = ny = 4
+    nz, u_in = 10, 0.03
+    shape = (nz, ny, nx)
+    u = np.zeros((3,) + shape)
+    u[2] = u_in
+    pb = W.Problem(name="plug", nx=nx, ny=ny, nz=nz, rho_r0=1.2, rho_b0=1.0, nu_r=0.02, nu_b=0.02, A=0.01,
+                   beta=0.7, faces=(W.PERIODIC,) * 4 + (W.FREESLIP, W.OUTFLOW), inflow=True, xc=1.5, yc=1.5,
+                   diameter=100.0, u_in=u_in, noise_rel=0.0, rho_r=np.full(shape, 1.2), rho_b=np.zeros(shape), u=u)
+    o = O.Oracle(pb)
+    f0 = o.populations()
+    o.step(60)
+    f1 = o.populations()
+    assert np.abs(f1 - f0).max() < 1e-14
+    f = o.fields()
+    assert np.abs(f["u"][2] - u_in).max() < 1e-14 and np.abs(f["rho_r"] - 1.2).max() < 1e-13
+
+
+def test_two_layer_poiseuille_viscosity_contrast(O):
+    """Red (nu_r) below blue (nu_b) between bounce-back walls, equal densities, no surface
+    tension, body force g along x.  In the steady state the shear stress balances the force,
+    nu(z) du/dz = -g (z - z0), with the local viscosity nu(z) = nu_b + a(z)(nu_r - nu_b) of
+    Sec. II (a = rho_r/rho of the final profile) and u = 0 on both walls (z = -1/2 and
+    z = H - 1/2).  Integrated numerically, that profile must match the lattice within
+    1 %: the enhanced equilibrium's Phi term is what keeps the viscous stress right where
+    nu varies, and a wrong interpolation of nu moves the profile by several per cent."""
+    H, g = 32, 1e-6
+    nu_r, nu_b = 0.05, 0.2
+    shape = (H, 1, 1)
+    z = np.arange(H, dtype=float)
+    zi = (H - 1) / 2.0
+    t = np.tanh(2.0 * (z - zi) / 4.0)
+    pb = W.Problem(name="layers", nx=1, ny=1, nz=H, rho_r0=1.0, rho_b0=1.0, nu_r=nu_r, nu_b=nu_b, A=0.0, beta=0.7,
+                   faces=(W.PERIODIC,) * 4 + (W.BOUNCEBACK,) * 2, force_model=1, g=(g, 0.0, 0.0), rho_ref=0.0,
+                   rho_r=(0.5 * (1.0 - t)).reshape(shape), rho_b=(0.5 * (1.0 + t)).reshape(shape),
+                   u=np.zeros((3,) + shape))
+    o = O.Oracle(pb)
+    o.step(40000)
+    f = o.fields()
+    ux = f["u"][0, :, 0, 0]
+    a = (f["rho_r"] / f["rho"])[:, 0, 0]
+    # fine grid over [-1/2, H - 1/2], nu interpolated linearly between cell centres
+    s = np.linspace(-0.5, H - 0.5, 64 * H + 1)
+    nu = nu_b + np.interp(s, z, a) * (nu_r - nu_b)
+    ds = s[1] - s[0]
+
+    def integral(fn):  # cumulative trapezoid from the lower wall
+        return np.concatenate([[0.0], np.cumsum(0.5 * (fn[1:] + fn[:-1]) * ds)])
+
+    I1 = integral(s / nu)
+    I0 = integral(1.0 / nu)
+    z0 = I1[-1] / I0[-1]  # u(H - 1/2) = 0
+    u_fine = -g * (I1 - z0 * I0)
+    exact = np.interp(z, s, u_fine)
+    err = np.abs(ux - exact).max() / np.abs(exact).max()
+    print(f"two-layer flow: max relative deviation {err:.3e}")
+    assert err < 0.01
