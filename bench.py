@@ -123,6 +123,40 @@ def copy_calibration(nbytes=1 << 30, reps=5):
                       "GBps_read_plus_write": 2 * nbytes / ms / 1e6}), flush=True)
 
 
+def sweep(steps: int, warmup: int, storage: str = "f16"):
+    """The regime-map sweep: 64 uneven jet cases (96^2 x 384 to 160^2 x 640, about 0.63 G
+    cells) advanced together by lbm_batch_step after the autotuner has chosen tile shapes."""
+    import torch
+    from paper_1705_03141_amd import lbm
+    from paper_1705_03141_amd import workloads as W
+
+    cases = W.regime_sweep()
+    ncells = sum(c.ncells for c in cases)
+    log(f"sweep: {len(cases)} cases, {ncells / 1e6:.0f} M cells, storage {storage}")
+    b = lbm.Batch(cases, storage=storage)
+    log("sweep: initialised; autotuning")
+    b.autotune(trial_steps=5)
+    b.step(warmup)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    wall = time.perf_counter() - t0
+    unstable = [k for k, c in enumerate(b.cases) if c.diagnostics()["unstable"]]
+    mlups = ncells * steps / wall / 1e6
+    std_bytes = 432.0 if storage == "f32" else 216.0
+    achieved = std_bytes * ncells / (b.last_step_ms() * 1e-3) / 1e9
+    print(json.dumps({"metric": "MLUPS, batched regime-map sweep (64 jet cases)", "value": mlups, "unit": "MLUPS",
+                      "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3 / steps, "dtype": f"f32 compute, {storage} storage",
+                      "config": {"workload": "regime_sweep_64_jets", "cases": len(cases), "cells": ncells},
+                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
+                                   "frac": achieved / PEAK_GBS, "bytes_per_cell": std_bytes},
+                      "unstable_cases": unstable,
+                      "regimes": {r: sum(1 for c in cases if c.regime == r) for r in ("I", "II", "III")}}), flush=True)
+    b.close()
+
+
 def interface_error(workload: str, steps: int):
     """Interface-position error of FP16 / BF16 storage against FP32 storage after `steps`
     steps (metrics.interface_position_error; lattice units)."""
@@ -160,6 +194,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead: time the 64-case regime-map sweep of uneven jets in one batch (FP16 storage)")
     ap.add_argument("--interface-error", choices=["rt", "jet"],
                     help="instead of timing: run the workload for --steps steps with FP32, FP16 and BF16 "
                          "storage and print the interface-position error of the half-precision runs")
@@ -174,6 +210,9 @@ def main():
         return
     if args.interface_error:
         interface_error(args.interface_error, args.steps)
+        return
+    if args.sweep:
+        sweep(args.steps, args.warmup)
         return
 
     from paper_1705_03141_amd import workloads as W

@@ -150,6 +150,35 @@ const char *lbm_last_error(const lbm_ctx *ctx);
 /* Free the device memory and the context.  NULL is ignored. */
 void lbm_destroy(lbm_ctx *ctx);
 
+/* ---------------------------------------------------------------- batches
+ * Several independent lattices (e.g. the jet cases of a regime map, Sec. IV C) advanced
+ * together: each step is one launch of the step kernel over all cases that share a storage
+ * type and tile shape, instead of one launch per case.
+ *
+ * lbm_batch_create: params points to ncases parameter blocks (validated as lbm_create); the
+ *   cases share hip_stream.  On success *out owns every case's device memory.
+ * lbm_batch_case: the context of case k (0 <= k < ncases), owned by the batch.  Use it with
+ *   lbm_set_inflow, lbm_init_fields, lbm_set_tiling, lbm_read_*, lbm_diagnostics and the
+ *   checkpoint calls; lbm_step on it returns LBM_ESTATE.  NULL for a bad index.
+ * lbm_batch_step: nsteps steps of every case (all cases must be initialised and at the same
+ *   step, else LBM_ESTATE).  Waits for work queued by the previous call before enqueuing.
+ * lbm_batch_autotune: chooses each case's tile shape by timing every supported shape on a
+ *   scratch lattice of the same size and physics for trial_steps steps; the cases' states
+ *   are not touched.  Results do not depend on the tile shape.
+ * lbm_batch_last_step_ms: mean wall time per step of the last lbm_batch_step call (HIP
+ *   events on the stream).
+ * Errors of batch calls: lbm_batch_last_error(batch). */
+typedef struct lbm_batch lbm_batch;
+lbm_status lbm_batch_create(const lbm_params *params, int ncases, void *hip_stream, lbm_batch **out);
+lbm_ctx *lbm_batch_case(lbm_batch *batch, int k);
+int lbm_batch_size(const lbm_batch *batch);
+lbm_status lbm_batch_autotune(lbm_batch *batch, int trial_steps);
+lbm_status lbm_batch_step(lbm_batch *batch, int nsteps);
+lbm_status lbm_batch_sync(lbm_batch *batch);
+double lbm_batch_last_step_ms(const lbm_batch *batch);
+const char *lbm_batch_last_error(const lbm_batch *batch);
+void lbm_batch_destroy(lbm_batch *batch);
+
 /* Diagnostic, not used by lbm_step: the step's per-cell collision arithmetic compiled for
  * the host, for checks without a GPU.  fr, fb: the cell's 27 pre-collision populations per
  * colour; grad_phi, grad_rho: 3 each; out_r, out_b: the 27 post-collision (recoloured)

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblbm.so")
 BUILD = os.path.join(HERE, "_build")
-UNITS = ["lbm_storage_f32.hip", "lbm_storage_f16.hip", "lbm_storage_bf16.hip", "lbm_dispatch.hip", "lbm_capi.hip"]
+UNITS = ["lbm_storage_f32.hip", "lbm_storage_f16.hip", "lbm_storage_bf16.hip", "lbm_dispatch.hip", "lbm_capi.hip",
+         "surr_ops.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are disabled: the compiler still vectorises plain float code.
 # FMA contraction is decided per source expression (-ffp-contract=on): every inlined copy of
@@ -67,7 +68,7 @@ def stale() -> bool:
         return True
     t = os.path.getmtime(LIB)
     deps = sources() + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    deps.append(os.path.join(INCLUDE, "lbm.h"))
+    deps += [os.path.join(INCLUDE, "lbm.h"), os.path.join(INCLUDE, "surrogate.h")]
     return any(os.path.getmtime(d) > t for d in deps)
 
 

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,7 +37,8 @@ struct lbm_ctx {
   int out_cur = 0;          // index of the outlet record of the latest time
   long long step = 0;
   bool initialised = false;
-  int tx = 0, ty = 0, zchunk = 0;  // 0: chosen at the first step (enqueue_one, auto_zchunk)
+  int tx = 0, ty = 0, zchunk = 0;  // 0: chosen at the first step (choose_tiling, auto_zchunk)
+  bool in_batch = false;           // advanced only by lbm_batch_step
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   std::string err;
@@ -282,30 +284,27 @@ static int auto_zchunk(const lbm_ctx* c) {
   return best;
 }
 
-static lbm_status enqueue_one(lbm_ctx* c) {
-  Geo& G = c->geo;
-  const bool init = c->step == 0;
-  if (G.face_hi == FACE_OUTFLOW) {
-    AuxArgs a = aux_args(c);
-    hipError_t e = launch_outlet((int)c->p.storage, a, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "outlet kernel");
-  }
-  StepArgs s{};
-  s.g_in = c->g[c->cur];
-  s.sc_in = c->sc[c->cur];
-  s.g_out = c->g[1 - c->cur];
-  s.sc_out = c->sc[1 - c->cur];
-  s.init = c->init;
-  s.outlet = c->outlet[1 - c->out_cur];
-  s.step = c->step;
-  s.init_mode = init ? 1 : 0;
+static void choose_tiling(lbm_ctx* c) {
   if (c->tx == 0) {
     // measured on MI355X: 64 x 4 tiles for FP32 state on rows of 64 cells or more, 32 x 8 otherwise
-    const bool wide = c->p.storage == LBM_F32 && G.nx >= 64;
+    const bool wide = c->p.storage == LBM_F32 && c->geo.nx >= 64;
     c->tx = wide ? 64 : 32;
     c->ty = wide ? 4 : 8;
   }
   if (c->zchunk < 1) c->zchunk = auto_zchunk(c);
+}
+
+// Arguments of the step kernel for the state of parity cur (outlet record out_cur).
+static void fill_step_args(const lbm_ctx* c, int cur, int out_cur, StepArgs& s) {
+  const Geo& G = c->geo;
+  s.g_in = c->g[cur];
+  s.sc_in = c->sc[cur];
+  s.g_out = c->g[1 - cur];
+  s.sc_out = c->sc[1 - cur];
+  s.init = c->init;
+  s.outlet = c->outlet[1 - out_cur];
+  s.step = c->step;
+  s.init_mode = c->step == 0 ? 1 : 0;
   s.zchunk = c->zchunk;
   s.tiles_x = (G.nx + c->tx - 1) / c->tx;
   s.tiles_y = (G.ny + c->ty - 1) / c->ty;
@@ -314,6 +313,18 @@ static lbm_status enqueue_one(lbm_ctx* c) {
   s.pc = c->pc;
   s.cp = c->cp;
   s.rates = c->rates;
+}
+
+static lbm_status enqueue_one(lbm_ctx* c) {
+  Geo& G = c->geo;
+  if (G.face_hi == FACE_OUTFLOW) {
+    AuxArgs a = aux_args(c);
+    hipError_t e = launch_outlet((int)c->p.storage, a, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "outlet kernel");
+  }
+  StepArgs s{};
+  choose_tiling(c);
+  fill_step_args(c, c->cur, c->out_cur, s);
   hipError_t e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step kernel");
   if (G.inflow) {
@@ -329,6 +340,7 @@ static lbm_status enqueue_one(lbm_ctx* c) {
 extern "C" lbm_status lbm_step(lbm_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   if (!c->initialised) return fail(c, LBM_ESTATE, "lbm_step before lbm_init_fields");
+  if (c->in_batch) return fail(c, LBM_ESTATE, "a case of a batch advances only with lbm_batch_step");
   if (nsteps == 0) return LBM_OK;
   LBM_HIP(c, hipEventRecord(c->ev0, c->stream));
   for (int k = 0; k < nsteps; ++k) {
@@ -495,6 +507,266 @@ extern "C" lbm_status lbm_load_state(lbm_ctx* c, const void* src, size_t bytes) 
   LBM_HIP(c, hipStreamSynchronize(c->stream));
   c->step = step;
   c->initialised = true;
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------- batches of lattices
+// Cases that share a storage type and tile shape form a group; one launch per group and step
+// advances all of them (batch_step_kernel).  Every case steps in lock-step, so the argument
+// tables of a group take two forms only (state parity 0 or 1) and are uploaded once per
+// lbm_batch_step call.
+struct BatchGroup {
+  int storage = 0, tx = 0, ty = 0;
+  std::vector<int> cases;               // indices into lbm_batch::c
+  StepArgs* d_args[2] = {nullptr, nullptr};  // device tables for parity 0 and 1
+  int* d_first = nullptr;               // device block offsets (ncases + 1)
+  int nblocks = 0;
+};
+
+struct lbm_batch {
+  std::vector<lbm_ctx*> c;
+  std::vector<BatchGroup> groups;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
+  std::string err;
+};
+
+static lbm_status batch_fail(lbm_batch* b, lbm_status st, const std::string& msg) {
+  if (b) b->err = msg;
+  return st;
+}
+
+static void free_groups(lbm_batch* b) {
+  for (auto& g : b->groups) {
+    for (int k = 0; k < 2; ++k)
+      if (g.d_args[k]) (void)hipFree(g.d_args[k]);
+    if (g.d_first) (void)hipFree(g.d_first);
+  }
+  b->groups.clear();
+}
+
+extern "C" void lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  free_groups(b);
+  for (lbm_ctx* c : b->c) lbm_destroy(c);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  delete b;
+}
+
+extern "C" lbm_status lbm_batch_create(const lbm_params* params, int ncases, void* hip_stream, lbm_batch** out) {
+  if (!params || !out || ncases < 1) return fail(nullptr, LBM_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  for (int k = 0; k < ncases; ++k) {
+    lbm_ctx* c = nullptr;
+    const lbm_status st = lbm_create(&params[k], hip_stream, &c);
+    if (st != LBM_OK) {
+      const std::string msg = "case " + std::to_string(k) + ": " + g_create_error;
+      lbm_batch_destroy(b);
+      return fail(nullptr, st, msg);
+    }
+    c->in_batch = true;
+    b->c.push_back(c);
+  }
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+    lbm_batch_destroy(b);
+    return fail(nullptr, LBM_EDEVICE, "event creation failed");
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+extern "C" lbm_ctx* lbm_batch_case(lbm_batch* b, int k) {
+  if (!b || k < 0 || k >= (int)b->c.size()) return nullptr;
+  return b->c[k];
+}
+
+extern "C" int lbm_batch_size(const lbm_batch* b) { return b ? (int)b->c.size() : 0; }
+
+extern "C" const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : ""; }
+
+// Tile shapes and z chunks of the cases not set by the caller or the autotuner.  Many cases
+// fill the GPU together, so a case takes whole columns (one z chunk) when the batch has at
+// least as many columns as the device holds workgroups.
+static void batch_tiling(lbm_batch* b) {
+  long long columns = 0, resident = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  for (lbm_ctx* c : b->c) {
+    if (c->tx == 0) {
+      const bool wide = c->p.storage == LBM_F32 && c->geo.nx >= 64;
+      c->tx = wide ? 64 : 32;
+      c->ty = wide ? 4 : 8;
+    }
+    columns += (long long)((c->geo.nx + c->tx - 1) / c->tx) * ((c->geo.ny + c->ty - 1) / c->ty);
+    resident = std::max<long long>(resident, step_resident_blocks((int)c->p.storage, c->tx, c->ty, dev));
+  }
+  for (lbm_ctx* c : b->c)
+    if (c->zchunk < 1) c->zchunk = columns >= resident ? c->geo.nz : auto_zchunk(c);
+}
+
+static lbm_status build_groups(lbm_batch* b) {
+  free_groups(b);
+  for (int k = 0; k < (int)b->c.size(); ++k) {
+    const lbm_ctx* c = b->c[k];
+    BatchGroup* g = nullptr;
+    for (auto& x : b->groups)
+      if (x.storage == (int)c->p.storage && x.tx == c->tx && x.ty == c->ty) g = &x;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->storage = (int)c->p.storage;
+      g->tx = c->tx;
+      g->ty = c->ty;
+    }
+    g->cases.push_back(k);
+  }
+  for (auto& g : b->groups) {
+    const int n = (int)g.cases.size();
+    std::vector<StepArgs> h[2];
+    std::vector<int> first(n + 1, 0);
+    for (int j = 0; j < n; ++j) {
+      const lbm_ctx* c = b->c[g.cases[j]];
+      for (int par = 0; par < 2; ++par) {
+        StepArgs s{};
+        fill_step_args(c, par, par, s);
+        h[par].push_back(s);
+      }
+      const StepArgs& s = h[0].back();
+      const long long blocks = (long long)s.tiles_x * s.tiles_y * s.nchunks;
+      first[j + 1] = first[j] + (int)((blocks + 7) / 8 * 8);
+    }
+    g.nblocks = first[n];
+    bool ok = true;
+    for (int par = 0; par < 2 && ok; ++par) {
+      ok = hipMalloc((void**)&g.d_args[par], n * sizeof(StepArgs)) == hipSuccess &&
+           hipMemcpy(g.d_args[par], h[par].data(), n * sizeof(StepArgs), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    ok = ok && hipMalloc((void**)&g.d_first, (n + 1) * sizeof(int)) == hipSuccess &&
+         hipMemcpy(g.d_first, first.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return batch_fail(b, LBM_ENOMEM, "batch table allocation failed");
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_step(lbm_batch* b, int nsteps) {
+  if (!b || nsteps < 0) return LBM_EINVAL;
+  if (nsteps == 0) return LBM_OK;
+  const lbm_ctx* c0 = b->c[0];
+  for (const lbm_ctx* c : b->c) {
+    if (!c->initialised) return batch_fail(b, LBM_ESTATE, "every case needs lbm_init_fields before lbm_batch_step");
+    // the outlet record of an outflow lattice flips with its state, so both share the parity
+    if (c->step != c0->step || c->cur != c0->cur || (c->geo.face_hi == FACE_OUTFLOW && c->out_cur != c->cur))
+      return batch_fail(b, LBM_ESTATE, "the cases of a batch must be at the same step");
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "stream synchronisation failed");
+  batch_tiling(b);
+  lbm_status st = build_groups(b);
+  if (st != LBM_OK) return st;
+  if (hipEventRecord(b->ev0, b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "event record failed");
+  for (int k = 0; k < nsteps; ++k) {
+    const int par = b->c[0]->cur;
+    const bool init = b->c[0]->step == 0;
+    for (lbm_ctx* c : b->c)
+      if (c->geo.face_hi == FACE_OUTFLOW) {
+        const hipError_t e = launch_outlet((int)c->p.storage, aux_args(c), b->stream);
+        if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("outlet kernel: ") + hipGetErrorString(e));
+      }
+    for (const auto& g : b->groups) {
+      const hipError_t e = launch_batch(g.storage, g.d_args[par], g.d_first, (int)g.cases.size(), g.nblocks, init,
+                                        g.tx, g.ty, b->stream);
+      if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("batch step kernel: ") + hipGetErrorString(e));
+    }
+    for (lbm_ctx* c : b->c) {
+      if (c->geo.inflow) {
+        StepArgs s{};
+        fill_step_args(c, c->cur, c->out_cur, s);
+        const hipError_t e = launch_inflow((int)c->p.storage, s, b->stream);
+        if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("inflow kernel: ") + hipGetErrorString(e));
+      }
+      c->cur = 1 - c->cur;
+      if (c->geo.face_hi == FACE_OUTFLOW) c->out_cur = 1 - c->out_cur;
+      c->step++;
+    }
+  }
+  if (hipEventRecord(b->ev1, b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "event record failed");
+  b->last_ms = -(double)nsteps;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_sync(lbm_batch* b) {
+  if (!b) return LBM_EINVAL;
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  return e == hipSuccess ? LBM_OK : batch_fail(b, LBM_EDEVICE, hipGetErrorString(e));
+}
+
+extern "C" double lbm_batch_last_step_ms(const lbm_batch* cb) {
+  lbm_batch* b = const_cast<lbm_batch*>(cb);
+  if (!b) return 0.0;
+  if (b->last_ms < 0.0) {
+    const double steps = -b->last_ms;
+    float ms = 0.0f;
+    if (hipEventSynchronize(b->ev1) != hipSuccess || hipEventElapsedTime(&ms, b->ev0, b->ev1) != hipSuccess) return 0.0;
+    b->last_ms = ms / steps;
+  }
+  return b->last_ms;
+}
+
+// Autotuner: for each distinct (lattice shape, storage) of the batch, time every supported
+// tile shape on a scratch lattice of that shape (blue fluid at rest, the case's physics) for
+// trial_steps steps and keep the fastest.  The cases' own states are not touched.
+extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps) {
+  if (!b || trial_steps < 1) return LBM_EINVAL;
+  static const int shapes[][2] = {{32, 8}, {64, 4}, {32, 4}};
+  struct Pick {
+    int nx, ny, nz, storage, tx, ty;
+  };
+  std::vector<Pick> picks;
+  for (lbm_ctx* c : b->c) {
+    const Geo& G = c->geo;
+    const Pick* found = nullptr;
+    for (const Pick& p : picks)
+      if (p.nx == G.nx && p.ny == G.ny && p.nz == G.nz && p.storage == (int)c->p.storage) found = &p;
+    if (!found) {
+      lbm_ctx* t = nullptr;
+      lbm_status st = lbm_create(&c->p, b->stream, &t);
+      if (st != LBM_OK) return batch_fail(b, st, "autotune: " + g_create_error);
+      const size_t n = (size_t)G.n;
+      std::vector<double> rr(n, 0.0), rb(n, c->p.rho_b0);
+      st = lbm_init_fields(t, rr.data(), rb.data(), nullptr);
+      double best = -1.0;
+      Pick p{G.nx, G.ny, G.nz, (int)c->p.storage, 32, 8};
+      for (const auto& sh : shapes) {
+        if (st != LBM_OK) break;
+        if ((st = lbm_set_tiling(t, sh[0], sh[1], 0)) != LBM_OK) break;
+        t->zchunk = 0;
+        if ((st = lbm_step(t, 1)) != LBM_OK || (st = lbm_step(t, trial_steps)) != LBM_OK) break;
+        const double ms = lbm_last_step_kernel_ms(t);
+        if (ms <= 0.0) {
+          st = LBM_EDEVICE;
+          break;
+        }
+        if (best < 0.0 || ms < best) {
+          best = ms;
+          p.tx = sh[0];
+          p.ty = sh[1];
+        }
+      }
+      const std::string terr = t->err;
+      lbm_destroy(t);
+      if (st != LBM_OK) return batch_fail(b, st, "autotune: " + terr);
+      picks.push_back(p);
+      found = &picks.back();
+    }
+    c->tx = found->tx;
+    c->ty = found->ty;
+    c->zchunk = 0;
+  }
   return LBM_OK;
 }
 

@@ -17,6 +17,16 @@ hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_batch(int storage, const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
+                        int tx, int ty, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_batch_T<float>(cases, first, ncases, nblocks, init, tx, ty, s);
+    case 1: return launch_batch_T<_Float16>(cases, first, ncases, nblocks, init, tx, ty, s);
+    case 2: return launch_batch_T<bf16>(cases, first, ncases, nblocks, init, tx, ty, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_inflow(int storage, const StepArgs& a, hipStream_t s) {
   switch (storage) {
     case 0: return launch_inflow_T<float>(a, s);

@@ -61,6 +61,9 @@ hipError_t launch_step_T(const StepArgs& a, int tx, int ty, hipStream_t s);
 template <typename T>
 hipError_t launch_inflow_T(const StepArgs& a, hipStream_t s);
 template <typename T>
+hipError_t launch_batch_T(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int tx, int ty,
+                          hipStream_t s);
+template <typename T>
 int step_resident_blocks_T(int tx, int ty, int device);
 template <typename T>
 hipError_t launch_outlet_T(const AuxArgs& a, hipStream_t s);
@@ -75,6 +78,11 @@ hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, lon
 // Dispatch on the storage code of lbm_params (0 FP32, 1 FP16, 2 BF16).
 bool step_tiling_supported(int tx, int ty);
 hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream_t s);
+// One step of several lattices in one launch: cases (device array of ncases argument blocks,
+// all with the same storage and tile shape), first (device, ncases + 1 block offsets, each a
+// multiple of 8), nblocks = first[ncases].
+hipError_t launch_batch(int storage, const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
+                        int tx, int ty, hipStream_t s);
 // Inflow sites of plane z = 0 written into the step's output state (after launch_step).
 hipError_t launch_inflow(int storage, const StepArgs& a, hipStream_t s);
 // Workgroups of the step kernel that fit on the device at once (0 if unknown).

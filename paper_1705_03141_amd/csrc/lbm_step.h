@@ -238,7 +238,7 @@ template <typename T, int TX, int TY, bool INIT>
 #ifndef LBM_STEP_WAVES_PER_EU
 #define LBM_STEP_WAVES_PER_EU 2
 #endif
-__global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU) step_kernel(const StepArgs A) {
+__device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb) {
   using Tile = StepTile<TX, TY>;
   constexpr int NT = Tile::kThreads, NR = Tile::kRing, SX = Tile::SX, NS = Tile::kStaged, DX = Tile::DX,
                 ND = Tile::kDense, KS = Tile::kStagePerThread;
@@ -256,12 +256,12 @@ __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU) step_kernel(co
   const unsigned slab_bytes = (unsigned)(Q * pb);           // 27 population planes of one z
   const unsigned sc_bytes = (unsigned)(5 * plane * 4);      // 5 scalar planes of one z
 
-  // block -> (z chunk, tile); XCD x receives blocks x, x + 8, ...: give it a contiguous range
-  int L = (int)blockIdx.x;
-  const int nb = (int)gridDim.x;
+  // block L of nb -> (z chunk, tile); XCD x receives blocks x, x + 8, ...: give it a
+  // contiguous range (nb and the first block of the range are multiples of 8 when remapped)
   if ((nb & 7) == 0) L = (L & 7) * (nb >> 3) + (L >> 3);
   const int ntiles = A.tiles_x * A.tiles_y;
   const int chunk = L / ntiles, tile = L - chunk * ntiles;
+  if (chunk >= A.nchunks) return;  // padding block of a batch (the whole block leaves)
   const int tyi = tile / A.tiles_x, txi = tile - tyi * A.tiles_x;
   const int x0 = txi * TX, y0 = tyi * TY;
   const int z0 = chunk * A.zchunk, z1 = min(z0 + A.zchunk, G.nz);
@@ -468,6 +468,28 @@ __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU) step_kernel(co
   }
 }
 
+template <typename T, int TX, int TY, bool INIT>
+__global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU) step_kernel(const StepArgs A) {
+  step_body<T, TX, TY, INIT>(A, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// Many lattices in one launch: case c owns blocks [first[c], first[c+1]) of the grid, each
+// range padded to a multiple of 8 blocks so that the XCD-aware numbering holds per case.
+template <typename T, int TX, int TY, bool INIT>
+__global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU)
+    batch_step_kernel(const StepArgs* __restrict__ cases, const int* __restrict__ first, int ncases) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = ncases;  // first[lo] <= b < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  step_body<T, TX, TY, INIT>(cases[lo], b - first[lo], first[lo + 1] - first[lo]);
+}
+
 // Inflow sites (R10) after a step: each emits the red equilibrium at rho_r0 and u_in(1 + eps xi)
 // e_z with Phi = 0 and no blue; the step kernel collided them like any cell.
 template <typename T>
@@ -502,6 +524,29 @@ hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL((step_kernel<T, TX, TY, false>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_batch_tile(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
+                             hipStream_t s) {
+  if (init)
+    hipLaunchKernelGGL((batch_step_kernel<T, TX, TY, true>), dim3((unsigned)nblocks), dim3(TX * TY), 0, s, cases,
+                       first, ncases);
+  else
+    hipLaunchKernelGGL((batch_step_kernel<T, TX, TY, false>), dim3((unsigned)nblocks), dim3(TX * TY), 0, s, cases,
+                       first, ncases);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_T(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int tx, int ty,
+                          hipStream_t s) {
+  if (tx == 32 && ty == 4) return launch_batch_tile<T, 32, 4>(cases, first, ncases, nblocks, init, s);
+  if (tx == 32 && ty == 8) return launch_batch_tile<T, 32, 8>(cases, first, ncases, nblocks, init, s);
+  if (tx == 64 && ty == 4) return launch_batch_tile<T, 64, 4>(cases, first, ncases, nblocks, init, s);
+  if (tx == 64 && ty == 8) return launch_batch_tile<T, 64, 8>(cases, first, ncases, nblocks, init, s);
+  if (tx == 32 && ty == 16) return launch_batch_tile<T, 32, 16>(cases, first, ncases, nblocks, init, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int TX, int TY>
@@ -542,6 +587,7 @@ int step_resident_blocks_T(int tx, int ty, int device) {
 
 #define LBM_INSTANTIATE_STEP(T)                                                 \
   template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t); \
+  template hipError_t launch_batch_T<T>(const StepArgs*, const int*, int, int, bool, int, int, hipStream_t); \
   template hipError_t launch_inflow_T<T>(const StepArgs&, hipStream_t);          \
   template int step_resident_blocks_T<T>(int, int, int);
 

@@ -90,11 +90,25 @@ def library():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_selftest_collide_host.argtypes = [P, _D, _D, _D, _D, _D, _D]
+        L.lbm_batch_create.argtypes = [P, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.lbm_batch_case.argtypes = [vp, ctypes.c_int]
+        L.lbm_batch_case.restype = vp
+        L.lbm_batch_size.argtypes = [vp]
+        L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int]
+        L.lbm_batch_step.argtypes = [vp, ctypes.c_int]
+        L.lbm_batch_sync.argtypes = [vp]
+        L.lbm_batch_last_step_ms.argtypes = [vp]
+        L.lbm_batch_last_step_ms.restype = ctypes.c_double
+        L.lbm_batch_last_error.argtypes = [vp]
+        L.lbm_batch_last_error.restype = ctypes.c_char_p
+        L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_destroy.restype = None
         for name in header_functions():
             getattr(L, name).restype = getattr(L, name).restype  # resolves every declared symbol
         for name in ("lbm_create", "lbm_init_fields", "lbm_set_inflow", "lbm_set_tiling", "lbm_step", "lbm_sync",
                      "lbm_read_field", "lbm_read_field_box", "lbm_read_populations", "lbm_save_state",
-                     "lbm_load_state", "lbm_diagnostics", "lbm_selftest_collide_host"):
+                     "lbm_load_state", "lbm_diagnostics", "lbm_selftest_collide_host", "lbm_batch_create",
+                     "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_size"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -183,11 +197,12 @@ class Lattice:
     """One lattice on the GPU, built from a :class:`workloads.Problem`."""
 
     def __init__(self, problem, storage: str = "f32", stream: Optional[int] = None, init: bool = True,
-                 tiling: Optional[tuple] = None):
+                 tiling: Optional[tuple] = None, _ctx=None):
         self.pb = problem
         self.storage = storage
         self.params = params_from_problem(problem, storage)
-        self.ctx = lbm_create(self.params, stream)
+        self._owned = _ctx is None
+        self.ctx = lbm_create(self.params, stream) if _ctx is None else _ctx
         self.shape = (problem.nz, problem.ny, problem.nx)
         self.n = problem.ncells
         if problem.inflow:
@@ -200,7 +215,8 @@ class Lattice:
 
     def close(self):
         if getattr(self, "ctx", None):
-            lbm_destroy(self.ctx)
+            if self._owned:
+                lbm_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):
@@ -262,6 +278,66 @@ class Lattice:
 
     def last_step_kernel_ms(self) -> float:
         return float(library().lbm_last_step_kernel_ms(self.ctx))
+
+
+class Batch:
+    """Several lattices advanced together (lbm_batch_*): one step-kernel launch per step for
+    all cases that share a storage type and tile shape.  ``cases[k]`` is a :class:`Lattice`
+    view of case k (read-back, diagnostics); the batch owns the device memory."""
+
+    def __init__(self, problems, storage: str = "f32", stream: Optional[int] = None, init: bool = True):
+        n = len(problems)
+        arr = (lbm_params * n)(*[params_from_problem(pb, storage) for pb in problems])
+        self.handle = ctypes.c_void_p()
+        st = library().lbm_batch_create(arr, n, ctypes.c_void_p(stream) if stream else None,
+                                        ctypes.byref(self.handle))
+        _check(None, st)
+        self.cases = []
+        for k, pb in enumerate(problems):
+            ctx = ctypes.c_void_p(library().lbm_batch_case(self.handle, k))
+            lat = Lattice(pb, storage=storage, init=False, _ctx=ctx)
+            if init:
+                if pb.rho_r is not None:
+                    lat.init_fields(pb.rho_r, pb.rho_b, pb.u)
+                else:  # fields made on demand, one case at a time
+                    rr, rb, u = pb.field_fn(*pb.origin, pb.nx, pb.ny, pb.nz)
+                    lat.init_fields(rr, rb, None if not np.any(u) else u)
+                    del rr, rb, u
+            self.cases.append(lat)
+
+    def _check(self, status):
+        if status != LBM_OK:
+            msg = library().lbm_batch_last_error(self.handle)
+            raise LbmError(status, msg.decode() if msg else "")
+
+    def autotune(self, trial_steps: int = 10):
+        self._check(library().lbm_batch_autotune(self.handle, int(trial_steps)))
+
+    def step(self, n: int = 1):
+        self._check(library().lbm_batch_step(self.handle, int(n)))
+
+    def sync(self):
+        self._check(library().lbm_batch_sync(self.handle))
+
+    def last_step_ms(self) -> float:
+        return float(library().lbm_batch_last_step_ms(self.handle))
+
+    @property
+    def ncells(self) -> int:
+        return sum(c.n for c in self.cases)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for c in self.cases:
+                c.ctx = None
+            library().lbm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def selftest_collide_host(problem, fr, fb, grad_phi, grad_rho):

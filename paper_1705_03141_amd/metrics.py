@@ -5,6 +5,9 @@ cells where run b sees the interface (|phi_b| < 0.9), the local displacement of 
 field is |phi_a - phi_b| / |grad phi_b| in lattice units (phi changes by |grad phi| per lattice
 unit across the interface, so a shift of the interface by d moves phi by d |grad phi|).
 Returns the mean and the maximum over those cells.
+
+Also: interface tracking of the paper's test problems (droplet half-axes, Rayleigh-Taylor
+front positions, jet leading edge) and the parity measures used by the tests.
 """
 from __future__ import annotations
 
@@ -32,6 +35,46 @@ def interface_position_error(phi_a: np.ndarray, phi_b: np.ndarray, band: float =
         return {"cells": 0, "mean_lu": 0.0, "max_lu": 0.0}
     disp = np.abs(phi_a[sel] - phi_b[sel]) / gmag[sel]
     return {"cells": int(sel.sum()), "mean_lu": float(disp.mean()), "max_lu": float(disp.max())}
+
+
+def crossing(profile: np.ndarray, start: int, step: int = 1) -> float:
+    """Position where a 1-D phase profile changes sign, searching from index `start` in
+    direction `step` (+1 or -1); linear interpolation between the two cells around the
+    change.  NaN if it never changes sign."""
+    s0 = np.sign(profile[start])
+    k = start
+    n = profile.shape[0]
+    while 0 <= k + step < n and np.sign(profile[k + step]) == s0:
+        k += step
+    if not 0 <= k + step < n:
+        return float("nan")
+    a, b = profile[k], profile[k + step]
+    return float(k + step * a / (a - b))
+
+
+def droplet_half_axes(phi: np.ndarray, center) -> tuple:
+    """Half-lengths of a droplet (phi > 0 inside) along x, y and z through its centre
+    (cell indices, arrays indexed [z, y, x]): the interface tracking of the oscillation
+    test (Sec. III B)."""
+    cx, cy, cz = (int(round(c)) for c in center)
+    return (crossing(phi[cz, cy, :], cx) - cx, crossing(phi[cz, :, cx], cy) - cy, crossing(phi[:, cy, cx], cz) - cz)
+
+
+def rt_front_positions(phi: np.ndarray) -> dict:
+    """Rayleigh-Taylor front positions (Sec. III C) on a W x W x H lattice with the heavy
+    fluid (phi > 0) at low z and the body force pushing it towards +z: the spike tip at the
+    column (0, 0), the bubble tip at (W/2, W/2) and the saddle at (0, W/2) of the
+    single-mode perturbation; each is the z where phi changes sign, searched from z = 0."""
+    W = phi.shape[2]
+    h = W // 2
+    return {"spike": crossing(phi[:, 0, 0], 0), "bubble": crossing(phi[:, h, h], 0), "saddle": crossing(phi[:, h, 0], 0)}
+
+
+def jet_leading_edge(phi: np.ndarray, threshold: float = 0.0) -> float:
+    """Largest z (cell index) holding injected fluid (phi > threshold) anywhere in its plane:
+    the leading edge of the jet (Sec. IV)."""
+    planes = np.nonzero((phi > threshold).any(axis=(1, 2)))[0]
+    return float(planes.max()) if planes.size else float("nan")
 
 
 def relative_errors(got: dict, ref: dict) -> dict:

@@ -1,0 +1,302 @@
+"""Learned surrogate of the lattice Boltzmann method (argument marshalling for include/
+surrogate.h; every operator runs in the HIP library).
+
+A 3-level 3-D convolutional encoder-decoder with 32 base channels maps the coarse-grained
+state of a jet, (phi, u / u_in) averaged over 4^3 blocks, to the change of that state over
+`horizon` steps of the method.  Weights and activations are BF16 on the matrix cores with
+FP32 accumulation and FP32 master weights (Adam).  torch provides device memory only.
+
+Architecture (channels-last, additive skips):
+  e1a = relu(conv 8->32)  e1 = relu(conv 32->32)          full resolution R
+  e2  = relu(conv 32->64 (pool e1))                        R/2
+  bt  = relu(conv 64->64 (pool e2))                        R/4
+  d2  = relu(conv 64->32 (up bt + e2))                     R/2
+  d1  = relu(conv 32->32 (up d2 + e1))                     R
+  y   = conv 32->32, channels 0..3 = change of (phi, ux, uy, uz)
+The input's channels 4..7 are zero (the convolution needs multiples of 8).
+
+The method stays the judge: `judge` runs the lattice over a calibration window and keeps
+the surrogate only where its interface error there is at most one coarse cell.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+from . import lbm as _lbm
+
+LAYERS = [("e1a", 8, 32), ("e1b", 32, 32), ("e2", 32, 64), ("bt", 64, 64), ("d2", 64, 32), ("d1", 32, 32),
+          ("out", 32, 32)]
+FIELDS = 4
+IN_CH = 8
+_bound = False
+
+
+def _lib():
+    global _bound
+    L = _lbm.library()
+    if not _bound:
+        vp, i, ll, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_float
+        L.surr_conv3d_fwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, i, i, i, vp]
+        L.surr_conv3d_flip_weights.argtypes = [vp, vp, i, i, vp]
+        L.surr_conv3d_dgrad.argtypes = [vp, vp, vp, i, i, i, i, i, i, vp]
+        L.surr_conv3d_wgrad_scratch_bytes.argtypes = [i, i, i, i, i, i]
+        L.surr_conv3d_wgrad_scratch_bytes.restype = ctypes.c_size_t
+        L.surr_conv3d_wgrad.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, i, i, vp]
+        L.surr_relu_bwd.argtypes = [vp, vp, vp, ll, vp]
+        L.surr_pool_fwd.argtypes = [vp, vp, i, i, i, i, i, vp]
+        L.surr_pool_bwd.argtypes = [vp, vp, i, i, i, i, i, vp]
+        L.surr_up_add_fwd.argtypes = [vp, vp, vp, i, i, i, i, i, vp]
+        L.surr_up_bwd.argtypes = [vp, vp, i, i, i, i, i, vp]
+        L.surr_mse.argtypes = [vp, vp, vp, vp, ll, i, i, vp]
+        L.surr_adam.argtypes = [vp, vp, vp, vp, vp, ll, f, f, f, f, i, vp]
+        L.surr_add.argtypes = [vp, vp, vp, ll, vp]
+        L.surr_to_bf16.argtypes = [vp, vp, ll, vp]
+        L.surr_to_f32.argtypes = [vp, vp, ll, vp]
+        _bound = True
+    return L
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _ok(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed ({rc})")
+
+
+class Network:
+    """The encoder-decoder on the GPU for inputs of shape (n, d, h, w); d, h, w divisible by 4."""
+
+    def __init__(self, n: int, d: int, h: int, w: int, seed: int = 0, lr: float = 1e-3, stream=None):
+        import torch
+
+        if d % 4 or h % 4 or w % 4:
+            raise ValueError("d, h and w must be multiples of 4")
+        self.torch = torch
+        self.shape = (n, d, h, w)
+        self.lr = lr
+        self.t = 0
+        self.stream = stream
+        dev = "cuda"
+        rng = np.random.default_rng(seed)
+        self.w32, self.wbf, self.wt, self.b, self.gw, self.gb, self.m, self.v = {}, {}, {}, {}, {}, {}, {}, {}
+        for name, cin, cout in LAYERS:
+            std = math.sqrt(2.0 / (27 * cin))
+            w = rng.normal(0.0, std, size=(27, cout, cin)).astype(np.float32)
+            if name == "out":
+                w *= 0.1  # start close to "no change"
+            self.w32[name] = torch.from_numpy(w).to(dev)
+            self.b[name] = torch.zeros(cout, dtype=torch.float32, device=dev)
+            self.wbf[name] = torch.empty((27, cout, cin), dtype=torch.int16, device=dev)
+            self.wt[name] = torch.empty((27, cin, cout), dtype=torch.int16, device=dev)
+            self.gw[name] = torch.zeros((27, cout, cin), dtype=torch.float32, device=dev)
+            self.gb[name] = torch.zeros(cout, dtype=torch.float32, device=dev)
+            for store in (self.m, self.v):
+                store[name] = (torch.zeros_like(self.w32[name]), torch.zeros_like(self.b[name]))
+        self._refresh_bf16()
+        self.act: Dict[str, "torch.Tensor"] = {}
+        self.grad: Dict[str, "torch.Tensor"] = {}
+
+        def buf(key, dims, c, dtype=torch.int16):
+            self.act[key] = torch.empty(dims + (c,), dtype=dtype, device=dev)
+
+        full, half, quarter = (n, d, h, w), (n, d // 2, h // 2, w // 2), (n, d // 4, h // 4, w // 4)
+        for key, dims, c in [("x", full, 8), ("e1a", full, 32), ("e1", full, 32), ("p1", half, 32), ("e2", half, 64),
+                             ("p2", quarter, 64), ("bt", quarter, 64), ("u2", half, 64), ("d2", half, 32),
+                             ("u1", full, 32), ("d1", full, 32)]:
+            buf(key, dims, c)
+        self.y = torch.empty(full + (32,), dtype=torch.float32, device=dev)
+        self.g_full32 = [torch.empty(full + (32,), dtype=torch.int16, device=dev) for _ in range(3)]
+        self.g_half64 = [torch.empty(half + (64,), dtype=torch.int16, device=dev) for _ in range(2)]
+        self.g_half32 = torch.empty(half + (32,), dtype=torch.int16, device=dev)
+        self.g_quarter64 = [torch.empty(quarter + (64,), dtype=torch.int16, device=dev) for _ in range(2)]
+        L = _lib()
+        sc = max(L.surr_conv3d_wgrad_scratch_bytes(n, d, h, w, cin, cout) for _, cin, cout in LAYERS)
+        self.scratch = torch.empty(int(sc) // 4 + 1, dtype=torch.float32, device=dev)
+        self.loss_part = torch.empty((n * d * h * w + 255) // 256, dtype=torch.float32, device=dev)
+
+    # ------------------------------------------------------------ parameters
+    def _refresh_bf16(self):
+        L = _lib()
+        for name, cin, cout in LAYERS:
+            _ok(L.surr_to_bf16(_p(self.w32[name]), _p(self.wbf[name]), self.w32[name].numel(), self.stream), "to_bf16")
+            _ok(L.surr_conv3d_flip_weights(_p(self.wbf[name]), _p(self.wt[name]), cin, cout, self.stream), "flip")
+
+    def set_params(self, params: dict):
+        """Load weights [27][cout][cin] and biases from host arrays."""
+        for name, _, _ in LAYERS:
+            w, b = params[name]
+            self.w32[name].copy_(self.torch.from_numpy(np.asarray(w, dtype=np.float32)))
+            self.b[name].copy_(self.torch.from_numpy(np.asarray(b, dtype=np.float32)))
+        self._refresh_bf16()
+
+    def get_params(self) -> dict:
+        return {name: (self.w32[name].cpu().numpy(), self.b[name].cpu().numpy()) for name, _, _ in LAYERS}
+
+    # ------------------------------------------------------------ forward / backward
+    def _conv(self, src, name, dst, dims, relu=True, out_f32=None):
+        L = _lib()
+        _, cin, cout = next(l for l in LAYERS if l[0] == name)
+        _ok(L.surr_conv3d_fwd(_p(src), _p(self.wbf[name]), _p(self.b[name]), _p(dst), _p(out_f32), *dims, cin, cout,
+                              1 if relu else 0, self.stream), f"conv {name}")
+
+    def set_input(self, x: np.ndarray):
+        """x: (n, d, h, w, 4) host array."""
+        t = self.torch
+        full = np.zeros(self.shape + (IN_CH,), dtype=np.float32)
+        full[..., :FIELDS] = x
+        xf = t.from_numpy(full).to("cuda")
+        _ok(_lib().surr_to_bf16(_p(xf), _p(self.act["x"]), xf.numel(), self.stream), "input")
+
+    def forward(self):
+        L = _lib()
+        n, d, h, w = self.shape
+        full, half, quarter = (n, d, h, w), (n, d // 2, h // 2, w // 2), (n, d // 4, h // 4, w // 4)
+        A = self.act
+        self._conv(A["x"], "e1a", A["e1a"], full)
+        self._conv(A["e1a"], "e1b", A["e1"], full)
+        _ok(L.surr_pool_fwd(_p(A["e1"]), _p(A["p1"]), *full, 32, self.stream), "pool1")
+        self._conv(A["p1"], "e2", A["e2"], half)
+        _ok(L.surr_pool_fwd(_p(A["e2"]), _p(A["p2"]), *half, 64, self.stream), "pool2")
+        self._conv(A["p2"], "bt", A["bt"], quarter)
+        _ok(L.surr_up_add_fwd(_p(A["bt"]), _p(A["e2"]), _p(A["u2"]), *quarter, 64, self.stream), "up2")
+        self._conv(A["u2"], "d2", A["d2"], half)
+        _ok(L.surr_up_add_fwd(_p(A["d2"]), _p(A["e1"]), _p(A["u1"]), *half, 32, self.stream), "up1")
+        self._conv(A["u1"], "d1", A["d1"], full)
+        self._conv(A["d1"], "out", None, full, relu=False, out_f32=self.y)
+        return self.y
+
+    def _dgrad(self, dout, name, din, dims):
+        _, cin, cout = next(l for l in LAYERS if l[0] == name)
+        _ok(_lib().surr_conv3d_dgrad(_p(dout), _p(self.wt[name]), _p(din), *dims, cin, cout, self.stream),
+            f"dgrad {name}")
+
+    def _wgrad(self, inp, dout, name, dims):
+        _, cin, cout = next(l for l in LAYERS if l[0] == name)
+        _ok(_lib().surr_conv3d_wgrad(_p(inp), _p(dout), _p(self.gw[name]), _p(self.gb[name]), _p(self.scratch), *dims,
+                                     cin, cout, self.stream), f"wgrad {name}")
+
+    def _relu_bwd(self, y, dy, dx):
+        _ok(_lib().surr_relu_bwd(_p(y), _p(dy), _p(dx), y.numel(), self.stream), "relu_bwd")
+
+    def _add(self, a, b, out):
+        _ok(_lib().surr_add(_p(a), _p(b), _p(out), a.numel(), self.stream), "add")
+
+    def backward(self, dy):
+        """dy: BF16 gradient of the loss with respect to the 32-channel output."""
+        L = _lib()
+        n, d, h, w = self.shape
+        full, half, quarter = (n, d, h, w), (n, d // 2, h // 2, w // 2), (n, d // 4, h // 4, w // 4)
+        A = self.act
+        g0, g1, g2 = self.g_full32
+        self._wgrad(A["d1"], dy, "out", full)
+        self._dgrad(dy, "out", g0, full)
+        self._relu_bwd(A["d1"], g0, g1)                      # g1 = d(d1 pre-activation)
+        self._wgrad(A["u1"], g1, "d1", full)
+        self._dgrad(g1, "d1", g2, full)                      # g2 = d(u1) = d(e1 skip) + up-part
+        _ok(L.surr_up_bwd(_p(g2), _p(self.g_half32), *full, 32, self.stream), "up1_bwd")  # d(d2)
+        h0, h1 = self.g_half64
+        dd2 = self.torch.empty_like(self.g_half32)
+        self._relu_bwd(A["d2"], self.g_half32, dd2)
+        self._wgrad(A["u2"], dd2, "d2", half)
+        self._dgrad(dd2, "d2", h0, half)                     # h0 = d(u2)
+        q0, q1 = self.g_quarter64
+        _ok(L.surr_up_bwd(_p(h0), _p(q0), *half, 64, self.stream), "up2_bwd")
+        self._relu_bwd(A["bt"], q0, q1)
+        self._wgrad(A["p2"], q1, "bt", quarter)
+        self._dgrad(q1, "bt", q0, quarter)                   # d(p2)
+        _ok(L.surr_pool_bwd(_p(q0), _p(h1), *half, 64, self.stream), "pool2_bwd")
+        self._add(h1, h0, h1)                                 # d(e2) = pool part + skip part
+        self._relu_bwd(A["e2"], h1, h0)
+        self._wgrad(A["p1"], h0, "e2", half)
+        self._dgrad(h0, "e2", self.g_half32, half)           # d(p1)
+        _ok(L.surr_pool_bwd(_p(self.g_half32), _p(g0), *full, 32, self.stream), "pool1_bwd")
+        self._add(g0, g2, g0)                                 # d(e1)
+        self._relu_bwd(A["e1"], g0, g1)
+        self._wgrad(A["e1a"], g1, "e1b", full)
+        self._dgrad(g1, "e1b", g0, full)
+        self._relu_bwd(A["e1a"], g0, g1)
+        self._wgrad(A["x"], g1, "e1a", full)
+
+    def loss_and_grad(self, target):
+        """target: (n, d, h, w, 4) FP32 device tensor.  Returns (loss, BF16 gradient)."""
+        dy = self.g_full32[2]
+        nv = self.shape[0] * self.shape[1] * self.shape[2] * self.shape[3]
+        _ok(_lib().surr_mse(_p(self.y), _p(target), _p(dy), _p(self.loss_part), nv, 32, FIELDS, self.stream), "mse")
+        loss = float(self.loss_part.cpu().numpy().astype(np.float64).sum()) / (nv * FIELDS)
+        return loss, dy
+
+    def adam_step(self, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        L = _lib()
+        for name, cin, cout in LAYERS:
+            mw, mb = self.m[name]
+            vw, vb = self.v[name]
+            _ok(L.surr_adam(_p(self.w32[name]), _p(self.wbf[name]), _p(self.gw[name]), _p(mw), _p(vw),
+                            self.w32[name].numel(), self.lr, beta1, beta2, eps, self.t, self.stream), "adam w")
+            bb = self.torch.empty(cout, dtype=self.torch.int16, device="cuda")
+            _ok(L.surr_adam(_p(self.b[name]), _p(bb), _p(self.gb[name]), _p(mb), _p(vb), cout, self.lr, beta1, beta2,
+                            eps, self.t, self.stream), "adam b")
+            _ok(L.surr_conv3d_flip_weights(_p(self.wbf[name]), _p(self.wt[name]), cin, cout, self.stream), "flip")
+
+    def train_step(self, x: np.ndarray, target: np.ndarray) -> float:
+        self.set_input(x)
+        self.forward()
+        tgt = self.torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32)).to("cuda")
+        loss, dy = self.loss_and_grad(tgt)
+        self.backward(dy)
+        self.adam_step()
+        return loss
+
+    def predict(self, x: np.ndarray) -> np.ndarray:
+        """State after the horizon: x + the network's change (host arrays, (n, d, h, w, 4))."""
+        self.set_input(x)
+        y = self.forward()
+        return x + y[..., :FIELDS].cpu().numpy()
+
+
+# ---------------------------------------------------------------- data from the method
+def coarse_state(lat, u_scale: float, factor: int = 4) -> np.ndarray:
+    """(phi, u / u_scale) of a lattice averaged over factor^3 blocks: (d, h, w, 4) with
+    (d, h, w) = (nz, ny, nx) / factor."""
+    nz, ny, nx = lat.shape
+    out = []
+    for name, s in (("phi", 1.0), ("ux", u_scale), ("uy", u_scale), ("uz", u_scale)):
+        f = lat.field(name) / s
+        out.append(f.reshape(nz // factor, factor, ny // factor, factor, nx // factor, factor).mean(axis=(1, 3, 5)))
+    return np.stack(out, axis=-1)
+
+
+def trajectories(problems, horizon: int, snapshots: int, storage: str = "f32") -> np.ndarray:
+    """Coarse states of every problem every `horizon` steps, run together as one batch:
+    array (snapshots + 1, ncases, d, h, w, 4)."""
+    b = _lbm.Batch(problems, storage=storage)
+    u = problems[0].u_in
+    states = [np.stack([coarse_state(c, u) for c in b.cases])]
+    for _ in range(snapshots):
+        b.step(horizon)
+        b.sync()
+        states.append(np.stack([coarse_state(c, u) for c in b.cases]))
+    b.close()
+    return np.stack(states)
+
+
+def interface_error_coarse(phi_a: np.ndarray, phi_b: np.ndarray) -> float:
+    """Mean interface displacement of phi_a against phi_b, in coarse cells."""
+    from .metrics import interface_position_error
+
+    return interface_position_error(phi_a, phi_b, periodic=(True, True, False))["mean_lu"]
+
+
+def judge(net: "Network", states_now: np.ndarray, states_next: np.ndarray, limit: float = 1.0):
+    """The method as judge: for each case, the surrogate's prediction of the next coarse state
+    against the lattice's own; cases whose interface moved by more than `limit` coarse cells
+    fall back to the lattice.  Returns (use_surrogate per case, interface error per case)."""
+    pred = net.predict(states_now)
+    errs = np.array([interface_error_coarse(pred[k, ..., 0], states_next[k, ..., 0]) for k in range(len(pred))])
+    return errs <= limit, errs

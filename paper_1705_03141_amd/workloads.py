@@ -193,7 +193,7 @@ def rayleigh_taylor(width: int = 128, height: Optional[int] = None, atwood: floa
 def jet(nx: int = 256, ny: int = 256, nz: int = 1024, diameter: float = 16.0, u_in: float = 0.04,
         gamma: float = 1.6, nu_c: float = 1.8e-4, eta: float = 1.0, weber: float = 220.0, froude: float = 8.5,
         A: Optional[float] = None, beta: float = 0.7, noise_rel: float = 0.01, seed: int = 3,
-        steps: int = 30000) -> Problem:
+        steps: int = 30000, fields: bool = True) -> Problem:
     """Liquid jet into an immiscible liquid (Sec. IV A): inflow disk on z = 0 with
     free-slip elsewhere on that plane, convective outflow on the last plane, periodic
     sides.  rho_j = 1; sigma from We = rho_j u^2 D / sigma; g from Fr = u^2 / (g D);
@@ -207,15 +207,16 @@ def jet(nx: int = 256, ny: int = 256, nz: int = 1024, diameter: float = 16.0, u_
     if A is None:
         A = 9.0 * sigma / (4.0 * (3.0 * nu_c + 0.5))
 
-    def fields(x0, y0, z0, wx, wy, wz):
+    def make_fields(x0, y0, z0, wx, wy, wz):
         shape = (wz, wy, wx)
         return np.zeros(shape), np.full(shape, rho_b0), np.zeros((3,) + shape)
 
-    return Problem(name="jet", nx=nx, ny=ny, nz=nz, rho_r0=rho_r0, rho_b0=rho_b0, nu_r=nu_j, nu_b=nu_c, A=A,
-                   beta=beta, faces=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, FREESLIP, OUTFLOW), force_model=1,
-                   g=(0.0, 0.0, g), rho_ref=rho_b0, inflow=True, xc=(nx - 1) / 2.0, yc=(ny - 1) / 2.0,
-                   diameter=diameter, u_in=u_in, noise_rel=noise_rel, seed=seed, steps=steps,
-                   field_fn=fields).with_fields()
+    pb = Problem(name="jet", nx=nx, ny=ny, nz=nz, rho_r0=rho_r0, rho_b0=rho_b0, nu_r=nu_j, nu_b=nu_c, A=A,
+                 beta=beta, faces=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, FREESLIP, OUTFLOW), force_model=1,
+                 g=(0.0, 0.0, g), rho_ref=rho_b0, inflow=True, xc=(nx - 1) / 2.0, yc=(ny - 1) / 2.0,
+                 diameter=diameter, u_in=u_in, noise_rel=noise_rel, seed=seed, steps=steps,
+                 field_fn=make_fields)
+    return pb.with_fields() if fields else pb
 
 
 # --- dimensionless groups of the jet (Sec. IV B, Eqs. (densityRatio)-(Froude)) -------------
@@ -237,6 +238,30 @@ def breakup_regime(Re: float, Oh: float) -> str:
     if Oh * Re < 22.0:
         return "II"
     return "III"
+
+
+def regime_sweep(ncases: int = 64, seed: int = 4, sizes=(96, 112, 128, 144, 160), diameters=(8, 16),
+                 fields: bool = False) -> list:
+    """Regime-map sweep of uneven jet cases (Sec. IV C): per case, drawn from a seeded
+    generator, nozzle D uniform on the integers of `diameters`, width L from `sizes` with
+    height 4 L, Re log-uniform on [100, 3400], Oh log-uniform on [0.005, 0.5], gamma
+    uniform on [1.2, 2.0]; u = 0.04, nu_j = nu_c = u D / Re, We = (Oh Re)^2, Fr = 8.5, 1 %
+    inflow noise.  Fields are made on demand unless `fields`."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for k in range(ncases):
+        D = int(rng.integers(diameters[0], diameters[1] + 1))
+        L = int(sizes[int(rng.integers(0, len(sizes)))])
+        Re = float(np.exp(rng.uniform(np.log(100.0), np.log(3400.0))))
+        Oh = float(np.exp(rng.uniform(np.log(0.005), np.log(0.5))))
+        gamma = float(rng.uniform(1.2, 2.0))
+        u = 0.04
+        pb = jet(nx=L, ny=L, nz=4 * L, diameter=float(D), u_in=u, gamma=gamma, nu_c=u * D / Re, eta=1.0,
+                 weber=(Oh * Re) ** 2, froude=8.5, noise_rel=0.01, seed=seed * 1000 + k, steps=5000, fields=fields)
+        pb.name = f"sweep{k:02d}_L{L}_D{D}_Re{Re:.0f}_Oh{Oh:.3f}_g{gamma:.2f}"
+        pb.regime = breakup_regime(Re, Oh)
+        cases.append(pb)
+    return cases
 
 
 UNIT_RATES = (0.0,) * 4 + (1.0,) * 23

@@ -1,0 +1,154 @@
+"""GPU tests of the learned surrogate (include/surrogate.h, paper_1705_03141_amd/surrogate.py).
+
+* each operator (convolution forward, data gradient, weight and bias gradient) against the
+  FP64 reference on BF16-representable inputs;
+* the whole network's weight gradients against the FP64 reference;
+* training on coarse-grained jet trajectories made by the lattice itself: the loss falls,
+  the trained network predicts held-out cases better than persistence and than the
+  untrained network, and the lattice as judge keeps it where its interface error is at
+  most one coarse cell.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import surrogate_ref as R
+from paper_1705_03141_amd import lbm
+from paper_1705_03141_amd import surrogate as S
+from paper_1705_03141_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bf16_round(x):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def to_dev_bf16(x):
+    import torch
+    u = np.ascontiguousarray(bf16_round(x).astype(np.float32)).view(np.uint32) >> 16
+    return torch.from_numpy(u.astype(np.uint16).view(np.int16)).to("cuda")
+
+
+def from_dev_bf16(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 64), (64, 32)])
+def test_conv_operators_against_reference(cin, cout):
+    import torch
+    rng = np.random.default_rng(cin + cout)
+    n, d, h, w = 2, 4, 6, 10
+    x = bf16_round(rng.normal(size=(n, d, h, w, cin)))
+    wt = bf16_round(rng.normal(size=(27, cout, cin)) * 0.1)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    dout = bf16_round(rng.normal(size=(n, d, h, w, cout)))
+    L = S._lib()
+    xd, wd, doutd = to_dev_bf16(x), to_dev_bf16(wt), to_dev_bf16(dout)
+    bd = torch.from_numpy(b.astype(np.float32)).to("cuda")
+    y32 = torch.empty((n, d, h, w, cout), dtype=torch.float32, device="cuda")
+    assert L.surr_conv3d_fwd(S._p(xd), S._p(wd), S._p(bd), None, S._p(y32), n, d, h, w, cin, cout, 0, None) == 0
+    e_fwd = rel(y32.cpu().numpy(), R.conv3d(x, wt, b))
+    # weight and bias gradients (FP32 out)
+    gw = torch.empty((27, cout, cin), dtype=torch.float32, device="cuda")
+    gb = torch.empty(cout, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(L.surr_conv3d_wgrad_scratch_bytes(n, d, h, w, cin, cout) // 4 + 1, dtype=torch.float32,
+                          device="cuda")
+    assert L.surr_conv3d_wgrad(S._p(xd), S._p(doutd), S._p(gw), S._p(gb), S._p(scratch), n, d, h, w, cin, cout,
+                               None) == 0
+    rw, rb = R.conv3d_wgrad(x, dout)
+    e_wg, e_bg = rel(gw.cpu().numpy(), rw), rel(gb.cpu().numpy(), rb)
+    msg = f"[conv {cin}->{cout}] fwd {e_fwd:.2e} wgrad {e_wg:.2e} bgrad {e_bg:.2e}"
+    # data gradient (cin multiple of 32 only)
+    if cin % 32 == 0:
+        w_t = torch.empty((27, cin, cout), dtype=torch.int16, device="cuda")
+        assert L.surr_conv3d_flip_weights(S._p(wd), S._p(w_t), cin, cout, None) == 0
+        din = torch.empty((n, d, h, w, cin), dtype=torch.int16, device="cuda")
+        assert L.surr_conv3d_dgrad(S._p(doutd), S._p(w_t), S._p(din), n, d, h, w, cin, cout, None) == 0
+        e_dg = rel(from_dev_bf16(din), R.conv3d_dgrad(dout, wt))
+        msg += f" dgrad {e_dg:.2e}"
+        assert e_dg < 1e-2
+    log(msg)
+    assert e_fwd < 1e-5 and e_wg < 1e-5 and e_bg < 1e-5
+
+
+def test_network_gradients_against_reference():
+    rng = np.random.default_rng(7)
+    n, d, h, w = 2, 8, 8, 16
+    params = R.init_params(seed=3)
+    params = {k: (bf16_round(v[0]), bf16_round(v[1])) for k, v in params.items()}
+    x = np.zeros((n, d, h, w, 8))
+    x[..., :4] = bf16_round(rng.normal(size=(n, d, h, w, 4)))
+    target = rng.normal(size=(n, d, h, w, 4)).astype(np.float32).astype(np.float64)
+    net = S.Network(n, d, h, w)
+    net.set_params(params)
+    net.set_input(x[..., :4])
+    net.forward()
+    import torch
+    loss_gpu, dy = net.loss_and_grad(torch.from_numpy(target.astype(np.float32)).to("cuda"))
+    net.backward(dy)
+    y, cache = R.forward(params, x)
+    loss_ref, dyr = R.mse(y, target)
+    g = R.backward(params, cache, dyr)
+    log(f"[network] loss gpu {loss_gpu:.6e} ref {loss_ref:.6e}")
+    assert abs(loss_gpu - loss_ref) / loss_ref < 2e-2
+    for name, _, _ in S.LAYERS:
+        a = net.gw[name].cpu().numpy().ravel()
+        r = g[name][0].ravel()
+        cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+        nerr = float(np.linalg.norm(a - r) / np.linalg.norm(r))
+        log(f"  {name}: cosine {cos:.5f} relative norm error {nerr:.3e}")
+        assert cos > 0.995 and nerr < 0.08, name
+
+
+def test_training_on_lattice_trajectories_beats_persistence():
+    horizon, snaps = 200, 8
+    train = W.regime_sweep(ncases=6, seed=21, sizes=(32,), diameters=(6, 8), fields=True)
+    held = W.regime_sweep(ncases=2, seed=99, sizes=(32,), diameters=(6, 8), fields=True)
+    t0 = time.perf_counter()
+    tr = S.trajectories(train, horizon, snaps)          # (snaps+1, 6, 32, 8, 8, 4)
+    te = S.trajectories(held, horizon, snaps)
+    t_lbm = time.perf_counter() - t0
+    log(f"[surrogate] trajectories: train {tr.shape}, held-out {te.shape}, {t_lbm:.1f} s")
+    net = S.Network(tr.shape[1], *tr.shape[2:5], seed=0, lr=2e-3)
+    net_te = S.Network(te.shape[1], *te.shape[2:5], seed=0)
+
+    def held_error(params):
+        net_te.set_params(params)
+        errs = [np.abs(net_te.predict(te[k]) - te[k + 1]).mean() for k in range(snaps)]
+        return float(np.mean(errs))
+
+    err_untrained = held_error(net.get_params())
+    persistence = float(np.mean([np.abs(te[k] - te[k + 1]).mean() for k in range(snaps)]))
+    rng = np.random.default_rng(0)
+    losses = []
+    for it in range(400):
+        k = int(rng.integers(0, snaps))
+        losses.append(net.train_step(tr[k], tr[k + 1] - tr[k]))
+    err_trained = held_error(net.get_params())
+    log(f"[surrogate] loss {np.mean(losses[:20]):.3e} -> {np.mean(losses[-20:]):.3e}; held-out mean |error|: "
+        f"persistence {persistence:.4e}, untrained {err_untrained:.4e}, trained {err_trained:.4e}")
+    # judge: the lattice checks one window per held-out case
+    use, ierr = S.judge(net_te, te[4], te[5])
+    t1 = time.perf_counter()
+    for _ in range(10):
+        net_te.predict(te[4])
+    t_net = (time.perf_counter() - t1) / 10
+    log(f"[surrogate] judge: interface error per held-out case {np.round(ierr, 3).tolist()} coarse cells, "
+        f"surrogate kept {use.tolist()}; one prediction {t_net * 1e3:.2f} ms for {horizon} steps of 2 cases")
+    assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:20])
+    assert err_trained < persistence and err_trained < err_untrained
