@@ -157,6 +157,38 @@ def sweep(steps: int, warmup: int, storage: str = "f16"):
     b.close()
 
 
+def surrogate_bench(steps: int, warmup: int):
+    """Training steps (forward, backward, Adam) of the surrogate on one 64 x 64 x 256 coarse
+    state; throughput of its convolutions against the dense BF16 MFMA peak (2.5 PFLOP/s)."""
+    import numpy as np
+    import torch
+    from paper_1705_03141_amd import surrogate as S
+
+    n, d, h, w = 1, 256, 64, 64
+    net = S.Network(n, d, h, w)
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(n, d, h, w, 4)).astype(np.float32) * 0.5
+    target = rng.normal(size=(n, d, h, w, 4)).astype(np.float32) * 0.01
+    for _ in range(warmup):
+        net.train_step(x, target)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x, target)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    nv = {"full": n * d * h * w, "half": n * d * h * w // 8, "quarter": n * d * h * w // 64}
+    res = {"e1a": "full", "e1b": "full", "e2": "half", "bt": "quarter", "d2": "half", "d1": "full", "out": "full"}
+    fwd = sum(2.0 * nv[res[name]] * 27 * cin * cout for name, cin, cout in S.LAYERS)
+    flops = 3.0 * fwd - 2.0 * nv["full"] * 27 * 8 * 32  # forward, weight gradient, data gradient (none for e1a)
+    tf = flops / dt / 1e12
+    print(json.dumps({"metric": "surrogate training step (forward + backward + Adam), 64x64x256x4 input",
+                      "value": dt * 1e3, "unit": "ms", "higher_is_better": False, "steps": steps,
+                      "conv_tflops": tf, "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0,
+                                                      "unit": "TFLOP/s", "frac": tf / 2500.0},
+                      "dtype": "bf16 MFMA, f32 accumulate"}), flush=True)
+
+
 def interface_error(workload: str, steps: int):
     """Interface-position error of FP16 / BF16 storage against FP32 storage after `steps`
     steps (metrics.interface_position_error; lattice units)."""
@@ -196,6 +228,8 @@ def main():
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--sweep", action="store_true",
                     help="instead: time the 64-case regime-map sweep of uneven jets in one batch (FP16 storage)")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="instead: time training steps of the surrogate network on the 64 x 64 x 256 x 4 input")
     ap.add_argument("--interface-error", choices=["rt", "jet"],
                     help="instead of timing: run the workload for --steps steps with FP32, FP16 and BF16 "
                          "storage and print the interface-position error of the half-precision runs")
@@ -213,6 +247,9 @@ def main():
         return
     if args.sweep:
         sweep(args.steps, args.warmup)
+        return
+    if args.surrogate:
+        surrogate_bench(args.steps, args.warmup)
         return
 
     from paper_1705_03141_amd import workloads as W

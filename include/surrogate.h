@@ -44,8 +44,10 @@ int surr_conv3d_wgrad(const uint16_t *in, const uint16_t *dout, float *dw, float
 int surr_relu_bwd(const uint16_t *y, const uint16_t *dy, uint16_t *dx, long long count, void *stream);
 
 /* 2x2x2 average pooling [n][d][h][w][c] -> [n][d/2][h/2][w/2][c] (d, h, w even) and its
- * gradient; nearest 2x upsampling with an added skip tensor, out = up(in) + skip, and its
- * gradient with respect to in (the gradient of skip is dout itself). */
+ * gradient; (d, h, w) are the dimensions of the fine tensor (in, din).  Nearest 2x
+ * upsampling with an added skip tensor, out = up(in) + skip, and its gradient with respect to
+ * in (the gradient of skip is dout itself); (d, h, w) are the dimensions of the coarse tensor
+ * (in, din), out and skip being 2d x 2h x 2w. */
 int surr_pool_fwd(const uint16_t *in, uint16_t *out, int n, int d, int h, int wd, int c, void *stream);
 int surr_pool_bwd(const uint16_t *dout, uint16_t *din, int n, int d, int h, int wd, int c, void *stream);
 int surr_up_add_fwd(const uint16_t *in, const uint16_t *skip, uint16_t *out, int n, int d, int h, int wd, int c,

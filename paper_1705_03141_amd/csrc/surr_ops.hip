@@ -98,44 +98,48 @@ __global__ void flip_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict
 
 // ---------------------------------------------------------------- weight gradient
 // dw[tap][co][ci] = sum_v dout[v][co] in[v + off(tap)][ci]: GEMM with M = cout, N = cin,
-// K = voxels.  One wave per (voxel chunk, tap, co tile, ci tile); partial sums per chunk go
-// to scratch and are added in chunk order by wgrad_reduce_kernel.
-constexpr int kChunk = 16384;
+// K = voxels.  The voxels are taken row by row (rows = (n, z, y), x fastest) in chunks of
+// whole rows; one wave per (chunk, tap, co tile, ci tile) steps through its rows 8 voxels
+// at a time, lane l holding voxels x0 + kq .. x0 + kq + 3.  Partial sums per chunk go to
+// scratch and are added in chunk order by chunk_sum_kernel.
+constexpr int kChunk = 16384;  // voxels per chunk (whole rows, at least one)
+
+__host__ __device__ inline int rows_per_chunk(int W) { return W >= kChunk ? 1 : kChunk / W; }
 
 __global__ void __launch_bounds__(64) wgrad_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ dout,
                                                    float* __restrict__ part, int D, int H, int W, int cin, int cout,
-                                                   long long nvox, int ci_tiles) {
+                                                   int nrows, int ci_tiles) {
   const int lane = threadIdx.x;
   const int chunk = blockIdx.x, tap = blockIdx.y;
   const int co0 = (blockIdx.z / ci_tiles) * 32, ci0 = (blockIdx.z % ci_tiles) * 32;
   const int kq = (lane >> 5) * 4;
   const int co = co0 + (lane & 31), ci = ci0 + (lane & 31);
   const bool ci_ok = ci < cin;
-  const long long vbeg = (long long)chunk * kChunk, vend = min(vbeg + kChunk, nvox);
+  const int dz = kTapOff[tap][0], dy = kTapOff[tap][1], dx = kTapOff[tap][2];
+  const int rpc = rows_per_chunk(W);
+  const int r0 = chunk * rpc, r1 = min(r0 + rpc, nrows);
   floatx16 acc = {};
-  for (long long vb = vbeg; vb < vend; vb += 8) {
-    bf16x4 a, b;
+  for (int row = r0; row < r1; ++row) {
+    const int y = row % H, z = (row / H) % D, nb = row / (H * D);
+    const int yy = y + dy, zz = z + dz;
+    const bool row_ok = ci_ok && yy >= 0 && yy < H && zz >= 0 && zz < D;
+    const long long orow = (long long)row * W;                      // first voxel of this row
+    const long long irow = ((long long)(nb * D + zz) * H + yy) * W;  // first voxel of the source row
+    for (int x0 = 0; x0 < W; x0 += 8) {
+      bf16x4 a, b;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long long v = vb + kq + j;
-      uint16_t av = 0, bv = 0;
-      if (v < vend) {
-        av = dout[v * cout + co];
-        long long t = v;
-        const int x = (int)(t % W);
-        t /= W;
-        const int y = (int)(t % H);
-        t /= H;
-        const int z = (int)(t % D);
-        const long long nb = t / D;
-        const int zz = z + kTapOff[tap][0], yy = y + kTapOff[tap][1], xx = x + kTapOff[tap][2];
-        if (ci_ok && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
-          bv = in[(((nb * D + zz) * H + yy) * (long long)W + xx) * cin + ci];
+      for (int j = 0; j < 4; ++j) {
+        const int x = x0 + kq + j, xx = x + dx;
+        uint16_t av = 0, bv = 0;
+        if (x < W) {
+          av = dout[(orow + x) * cout + co];
+          if (row_ok && xx >= 0 && xx < W) bv = in[(irow + xx) * cin + ci];
+        }
+        a[j] = (short)av;
+        b[j] = (short)bv;
       }
-      a[j] = (short)av;
-      b[j] = (short)bv;
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
   }
   // acc row m = co0 + 8 (r/4) + kq + r%4, column n = ci0 + lane % 32
   float* dst = part + (long long)chunk * 27 * cout * cin + (long long)tap * cout * cin;
@@ -146,14 +150,15 @@ __global__ void __launch_bounds__(64) wgrad_kernel(const uint16_t* __restrict__ 
   }
 }
 
-// dbias partials: block = chunk, thread t sums channel t % cout over voxels t / cout + P k.
+// dbias partials: block = chunk of rows, thread t sums channel t % cout over its voxels.
 __global__ void __launch_bounds__(256) bias_part_kernel(const uint16_t* __restrict__ dout, float* __restrict__ part,
-                                                        int cout, long long nvox) {
+                                                        int cout, int W, int nrows) {
   __shared__ float s[256];
   const int t = threadIdx.x;
   const int P = 256 / cout;
   const int c = t % cout, p = t / cout;
-  const long long vbeg = (long long)blockIdx.x * kChunk, vend = min(vbeg + kChunk, nvox);
+  const int rpc = rows_per_chunk(W);
+  const long long vbeg = (long long)blockIdx.x * rpc * W, vend = (long long)min(blockIdx.x * rpc + rpc, nrows) * W;
   float acc = 0.0f;
   if (p < P)
     for (long long v = vbeg + p; v < vend; v += P) acc += bf2f(dout[v * cout + c]);
@@ -343,8 +348,9 @@ extern "C" int surr_conv3d_dgrad(const uint16_t* dout, const uint16_t* w_t, uint
 }
 
 extern "C" size_t surr_conv3d_wgrad_scratch_bytes(int n, int d, int h, int wd, int cin, int cout) {
-  const long long nvox = (long long)n * d * h * wd;
-  const long long nchunks = (nvox + kChunk - 1) / kChunk;
+  if (n < 1 || d < 1 || h < 1 || wd < 1 || cin < 1 || cout < 1) return 0;
+  const long long nrows = (long long)n * d * h;
+  const long long nchunks = (nrows + rows_per_chunk(wd) - 1) / rows_per_chunk(wd);
   return (size_t)nchunks * ((size_t)27 * cout * cin + (size_t)cout) * sizeof(float);
 }
 
@@ -353,17 +359,19 @@ extern "C" int surr_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float
   if (n < 1 || d < 1 || h < 1 || wd < 1 || cin < 8 || cin % 8 || cout < 32 || cout % 32 || cout > 256 || !in ||
       !dout || !dw || !scratch)
     return -1;
-  const long long nvox = (long long)n * d * h * wd;
-  const int nchunks = (int)((nvox + kChunk - 1) / kChunk);
+  const long long nrows_ll = (long long)n * d * h;
+  if (nrows_ll * wd >= (1LL << 31)) return -1;
+  const int nrows = (int)nrows_ll;
+  const int nchunks = (nrows + rows_per_chunk(wd) - 1) / rows_per_chunk(wd);
   const int ci_tiles = (cin + 31) / 32;
   float* part = static_cast<float*>(scratch);
   float* bpart = part + (size_t)nchunks * 27 * cout * cin;
   hipLaunchKernelGGL(wgrad_kernel, dim3(nchunks, 27, (cout / 32) * ci_tiles), dim3(64), 0, S(stream), in, dout, part, d,
-                     h, wd, cin, cout, nvox, ci_tiles);
+                     h, wd, cin, cout, nrows, ci_tiles);
   const long long len = 27LL * cout * cin;
   hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(len, 256)), dim3(256), 0, S(stream), part, dw, len, nchunks);
   if (dbias) {
-    hipLaunchKernelGGL(bias_part_kernel, dim3(nchunks), dim3(256), 0, S(stream), dout, bpart, cout, nvox);
+    hipLaunchKernelGGL(bias_part_kernel, dim3(nchunks), dim3(256), 0, S(stream), dout, bpart, cout, wd, nrows);
     hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(cout, 256)), dim3(256), 0, S(stream), bpart, dbias,
                        (long long)cout, nchunks);
   }

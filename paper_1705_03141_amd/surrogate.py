@@ -72,7 +72,8 @@ def _ok(rc, what):
 class Network:
     """The encoder-decoder on the GPU for inputs of shape (n, d, h, w); d, h, w divisible by 4."""
 
-    def __init__(self, n: int, d: int, h: int, w: int, seed: int = 0, lr: float = 1e-3, stream=None):
+    def __init__(self, n: int, d: int, h: int, w: int, seed: int = 0, lr: float = 1e-3, stream=None,
+                 device: str = "cuda"):
         import torch
 
         if d % 4 or h % 4 or w % 4:
@@ -82,15 +83,15 @@ class Network:
         self.lr = lr
         self.t = 0
         self.stream = stream
-        dev = "cuda"
+        self.device = dev = device
         rng = np.random.default_rng(seed)
         self.w32, self.wbf, self.wt, self.b, self.gw, self.gb, self.m, self.v = {}, {}, {}, {}, {}, {}, {}, {}
         for name, cin, cout in LAYERS:
             std = math.sqrt(2.0 / (27 * cin))
-            w = rng.normal(0.0, std, size=(27, cout, cin)).astype(np.float32)
+            w0 = rng.normal(0.0, std, size=(27, cout, cin)).astype(np.float32)
             if name == "out":
-                w *= 0.1  # start close to "no change"
-            self.w32[name] = torch.from_numpy(w).to(dev)
+                w0 *= 0.1  # start close to "no change"
+            self.w32[name] = torch.from_numpy(w0).to(dev)
             self.b[name] = torch.zeros(cout, dtype=torch.float32, device=dev)
             self.wbf[name] = torch.empty((27, cout, cin), dtype=torch.int16, device=dev)
             self.wt[name] = torch.empty((27, cin, cout), dtype=torch.int16, device=dev)
@@ -150,7 +151,7 @@ class Network:
         t = self.torch
         full = np.zeros(self.shape + (IN_CH,), dtype=np.float32)
         full[..., :FIELDS] = x
-        xf = t.from_numpy(full).to("cuda")
+        xf = t.from_numpy(full).to(self.device)
         _ok(_lib().surr_to_bf16(_p(xf), _p(self.act["x"]), xf.numel(), self.stream), "input")
 
     def forward(self):
@@ -199,14 +200,14 @@ class Network:
         self._relu_bwd(A["d1"], g0, g1)                      # g1 = d(d1 pre-activation)
         self._wgrad(A["u1"], g1, "d1", full)
         self._dgrad(g1, "d1", g2, full)                      # g2 = d(u1) = d(e1 skip) + up-part
-        _ok(L.surr_up_bwd(_p(g2), _p(self.g_half32), *full, 32, self.stream), "up1_bwd")  # d(d2)
+        _ok(L.surr_up_bwd(_p(g2), _p(self.g_half32), *half, 32, self.stream), "up1_bwd")  # d(d2)
         h0, h1 = self.g_half64
         dd2 = self.torch.empty_like(self.g_half32)
         self._relu_bwd(A["d2"], self.g_half32, dd2)
         self._wgrad(A["u2"], dd2, "d2", half)
         self._dgrad(dd2, "d2", h0, half)                     # h0 = d(u2)
         q0, q1 = self.g_quarter64
-        _ok(L.surr_up_bwd(_p(h0), _p(q0), *half, 64, self.stream), "up2_bwd")
+        _ok(L.surr_up_bwd(_p(h0), _p(q0), *quarter, 64, self.stream), "up2_bwd")
         self._relu_bwd(A["bt"], q0, q1)
         self._wgrad(A["p2"], q1, "bt", quarter)
         self._dgrad(q1, "bt", q0, quarter)                   # d(p2)
@@ -239,7 +240,7 @@ class Network:
             vw, vb = self.v[name]
             _ok(L.surr_adam(_p(self.w32[name]), _p(self.wbf[name]), _p(self.gw[name]), _p(mw), _p(vw),
                             self.w32[name].numel(), self.lr, beta1, beta2, eps, self.t, self.stream), "adam w")
-            bb = self.torch.empty(cout, dtype=self.torch.int16, device="cuda")
+            bb = self.torch.empty(cout, dtype=self.torch.int16, device=self.device)
             _ok(L.surr_adam(_p(self.b[name]), _p(bb), _p(self.gb[name]), _p(mb), _p(vb), cout, self.lr, beta1, beta2,
                             eps, self.t, self.stream), "adam b")
             _ok(L.surr_conv3d_flip_weights(_p(self.wbf[name]), _p(self.wt[name]), cin, cout, self.stream), "flip")
@@ -247,7 +248,7 @@ class Network:
     def train_step(self, x: np.ndarray, target: np.ndarray) -> float:
         self.set_input(x)
         self.forward()
-        tgt = self.torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32)).to("cuda")
+        tgt = self.torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32)).to(self.device)
         loss, dy = self.loss_and_grad(tgt)
         self.backward(dy)
         self.adam_step()

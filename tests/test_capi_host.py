@@ -25,6 +25,14 @@ def test_exports_every_declared_symbol(L):
     assert len(names) >= 17
     for n in names:
         assert hasattr(L, n), n
+    # the surrogate's operators (include/surrogate.h) live in the same library
+    import os
+    import re
+    with open(os.path.join(os.path.dirname(lbm.HEADER), "surrogate.h")) as fh:
+        surr = set(re.findall(r"^\s*(?:[a-z_0-9]+\s+)+\**\s*(surr_[a-z_0-9]+)\s*\(", fh.read(), re.M))
+    assert len(surr) >= 14
+    for n in surr:
+        assert hasattr(L, n), n
 
 
 def _expect(status_code, problem, **override):

@@ -1,0 +1,188 @@
+"""CPU check of the surrogate network's orchestration (paper_1705_03141_amd/surrogate.py):
+every call it makes into include/surrogate.h is answered by a numpy stand-in that first
+checks each buffer against the sizes passed (the kernels would otherwise read or write out
+of bounds) and then applies the FP64 reference operator.  One training step must then give
+the reference network's gradients (BF16 rounding of the activations aside)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate_ref as R
+from paper_1705_03141_amd import surrogate as S
+
+
+def _f32_of_bf16(t):
+    return (t.numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _store_bf16(t, x):
+    x = np.ascontiguousarray(x, dtype=np.float32).ravel()
+    u = x.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    t.view(-1)[: u.size].copy_(torch.from_numpy(u.view(np.int16)))
+
+
+def _need(t, count, what):
+    assert t.numel() >= count, f"{what}: buffer of {t.numel()} elements for {count}"
+
+
+class StandIn:
+    """Numpy stand-ins of the C-ABI operators, with buffer-size checks."""
+
+    def surr_conv3d_fwd(self, inp, w, bias, out, out_f32, n, d, h, wd, cin, cout, relu, stream):
+        nv = n * d * h * wd
+        _need(inp, nv * cin, "conv in")
+        _need(w, 27 * cout * cin, "conv w")
+        x = _f32_of_bf16(inp)[: nv * cin].reshape(n, d, h, wd, cin)
+        ww = _f32_of_bf16(w)[: 27 * cout * cin].reshape(27, cout, cin)
+        b = bias.numpy().astype(np.float64) if bias is not None else None
+        y = R.conv3d(x, ww, b)
+        if relu:
+            y = R.relu(y)
+        if out_f32 is not None:
+            _need(out_f32, nv * cout, "conv out_f32")
+            out_f32.view(-1)[: nv * cout].copy_(torch.from_numpy(y.astype(np.float32).ravel()))
+        else:
+            _need(out, nv * cout, "conv out")
+            _store_bf16(out, y)
+        return 0
+
+    def surr_conv3d_flip_weights(self, w, wt, cin, cout, stream):
+        _need(w, 27 * cin * cout, "flip w")
+        _need(wt, 27 * cin * cout, "flip w_t")
+        ww = _f32_of_bf16(w)[: 27 * cout * cin].reshape(27, cout, cin)
+        _store_bf16(wt, ww[::-1].transpose(0, 2, 1))
+        return 0
+
+    def surr_conv3d_dgrad(self, dout, wt, din, n, d, h, wd, cin, cout, stream):
+        return self.surr_conv3d_fwd(dout, wt, None, din, None, n, d, h, wd, cout, cin, 0, stream)
+
+    def surr_conv3d_wgrad_scratch_bytes(self, n, d, h, wd, cin, cout):
+        return 4
+
+    def surr_conv3d_wgrad(self, inp, dout, dw, db, scratch, n, d, h, wd, cin, cout, stream):
+        nv = n * d * h * wd
+        _need(inp, nv * cin, "wgrad in")
+        _need(dout, nv * cout, "wgrad dout")
+        _need(dw, 27 * cout * cin, "wgrad dw")
+        x = _f32_of_bf16(inp)[: nv * cin].reshape(n, d, h, wd, cin)
+        g = _f32_of_bf16(dout)[: nv * cout].reshape(n, d, h, wd, cout)
+        a, b = R.conv3d_wgrad(x, g)
+        dw.view(-1)[: a.size].copy_(torch.from_numpy(a.astype(np.float32).ravel()))
+        if db is not None:
+            _need(db, cout, "wgrad db")
+            db.copy_(torch.from_numpy(b.astype(np.float32)))
+        return 0
+
+    def surr_relu_bwd(self, y, dy, dx, count, stream):
+        for t, nm in ((y, "y"), (dy, "dy"), (dx, "dx")):
+            _need(t, count, "relu_bwd " + nm)
+        g = _f32_of_bf16(dy)[:count] * (_f32_of_bf16(y)[:count] > 0)
+        _store_bf16(dx, g)
+        return 0
+
+    def surr_pool_fwd(self, inp, out, n, d, h, wd, c, stream):
+        _need(inp, n * d * h * wd * c, "pool in")
+        _need(out, n * d * h * wd * c // 8, "pool out")
+        _store_bf16(out, R.pool(_f32_of_bf16(inp)[: n * d * h * wd * c].reshape(n, d, h, wd, c)))
+        return 0
+
+    def surr_pool_bwd(self, dout, din, n, d, h, wd, c, stream):
+        _need(dout, n * d * h * wd * c // 8, "pool_bwd dout")
+        _need(din, n * d * h * wd * c, "pool_bwd din")
+        g = _f32_of_bf16(dout)[: n * d * h * wd * c // 8].reshape(n, d // 2, h // 2, wd // 2, c)
+        _store_bf16(din, R.pool_bwd(g))
+        return 0
+
+    def surr_up_add_fwd(self, inp, skip, out, n, d, h, wd, c, stream):
+        _need(inp, n * d * h * wd * c, "up in")
+        _need(skip, 8 * n * d * h * wd * c, "up skip")
+        _need(out, 8 * n * d * h * wd * c, "up out")
+        x = _f32_of_bf16(inp)[: n * d * h * wd * c].reshape(n, d, h, wd, c)
+        s = _f32_of_bf16(skip)[: 8 * n * d * h * wd * c].reshape(n, 2 * d, 2 * h, 2 * wd, c)
+        _store_bf16(out, R.up(x) + s)
+        return 0
+
+    def surr_up_bwd(self, dout, din, n, d, h, wd, c, stream):
+        _need(dout, 8 * n * d * h * wd * c, "up_bwd dout")
+        _need(din, n * d * h * wd * c, "up_bwd din")
+        g = _f32_of_bf16(dout)[: 8 * n * d * h * wd * c].reshape(n, 2 * d, 2 * h, 2 * wd, c)
+        _store_bf16(din, R.up_bwd(g))
+        return 0
+
+    def surr_mse(self, pred, target, dpred, loss_part, count, stride, used, stream):
+        _need(pred, count * stride, "mse pred")
+        _need(target, count * used, "mse target")
+        _need(dpred, count * stride, "mse dpred")
+        p = pred.numpy().astype(np.float64)[: count * stride].reshape(count, stride)
+        t = target.numpy().astype(np.float64).reshape(-1)[: count * used].reshape(count, used)
+        e = p[:, :used] - t
+        g = np.zeros_like(p)
+        g[:, :used] = 2 * e / (count * used)
+        _store_bf16(dpred, g)
+        loss_part.zero_()
+        loss_part[0] = float((e * e).sum())
+        return 0
+
+    def surr_adam(self, w, wb, g, m, v, count, lr, b1, b2, eps, t, stream):
+        for x, nm in ((w, "w"), (wb, "wb"), (g, "g"), (m, "m"), (v, "v")):
+            _need(x, count, "adam " + nm)
+        gg = g.numpy().astype(np.float64)
+        mm = b1 * m.numpy() + (1 - b1) * gg
+        vv = b2 * v.numpy() + (1 - b2) * gg * gg
+        ww = w.numpy() - lr * (mm / (1 - b1 ** t)) / (np.sqrt(vv / (1 - b2 ** t)) + eps)
+        m.copy_(torch.from_numpy(mm.astype(np.float32)))
+        v.copy_(torch.from_numpy(vv.astype(np.float32)))
+        w.copy_(torch.from_numpy(ww.astype(np.float32)))
+        _store_bf16(wb, ww)
+        return 0
+
+    def surr_add(self, a, b, out, count, stream):
+        for x, nm in ((a, "a"), (b, "b"), (out, "out")):
+            _need(x, count, "add " + nm)
+        _store_bf16(out, _f32_of_bf16(a)[:count] + _f32_of_bf16(b)[:count])
+        return 0
+
+    def surr_to_bf16(self, x, y, count, stream):
+        _need(x, count, "to_bf16 x")
+        _need(y, count, "to_bf16 y")
+        _store_bf16(y, x.numpy().astype(np.float64).ravel()[:count])
+        return 0
+
+    def surr_to_f32(self, x, y, count, stream):
+        y.view(-1)[:count].copy_(torch.from_numpy(_f32_of_bf16(x)[:count].astype(np.float32)))
+        return 0
+
+
+@pytest.fixture
+def standin(monkeypatch):
+    monkeypatch.setattr(S, "_lib", lambda: StandIn())
+    monkeypatch.setattr(S, "_p", lambda t: t)
+
+
+def test_training_step_wiring_matches_reference(standin):
+    rng = np.random.default_rng(1)
+    n, d, h, w = 2, 8, 4, 8
+    net = S.Network(n, d, h, w, seed=3, device="cpu")
+    params = net.get_params()
+    x = rng.normal(size=(n, d, h, w, 4)).astype(np.float32)
+    target = (rng.normal(size=(n, d, h, w, 4)) * 0.1).astype(np.float32)
+    net.set_input(x)
+    net.forward()
+    loss, dy = net.loss_and_grad(torch.from_numpy(target))
+    net.backward(dy)
+    # reference on the BF16-rounded weights and input the network saw
+    p = {k: (_f32_of_bf16(net.wbf[k]).reshape(v[0].shape), v[1].astype(np.float64)) for k, v in params.items()}
+    xx = np.zeros((n, d, h, w, 8))
+    xx[..., :4] = _f32_of_bf16(net.act["x"]).reshape(n, d, h, w, 8)[..., :4]
+    y, cache = R.forward(p, xx)
+    loss_ref, dyr = R.mse(y, target.astype(np.float64))
+    g = R.backward(p, cache, dyr)
+    assert abs(loss - loss_ref) / loss_ref < 1e-2
+    for name, _, _ in S.LAYERS:
+        a = net.gw[name].numpy().ravel().astype(np.float64)
+        r = g[name][0].ravel()
+        cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+        assert cos > 0.99, (name, cos)
+    net.adam_step()
+    assert net.t == 1
