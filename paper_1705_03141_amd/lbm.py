@@ -64,6 +64,13 @@ def library():
         from . import build as _build
         if _build.stale():
             _build.build()
+        # torch ships its own HIP runtime under the same library name as the system's; loading
+        # it first makes the process use one runtime for both (the second one loaded would
+        # otherwise resolve to the first and find no GPU)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER(lbm_params)
         vp = ctypes.c_void_p
