@@ -591,8 +591,11 @@ extern "C" int lbm_batch_size(const lbm_batch* b) { return b ? (int)b->c.size() 
 extern "C" const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : ""; }
 
 // Tile shapes and z chunks of the cases not set by the caller or the autotuner.  Many cases
-// fill the GPU together, so a case takes whole columns (one z chunk) when the batch has at
-// least as many columns as the device holds workgroups.
+// fill the GPU together; when the batch has at least as many columns as the device holds
+// workgroups, every case is cut into chunks of kBatchChunk planes so that the workgroups of
+// uneven cases carry equal work.
+static constexpr int kBatchChunk = 64;
+
 static void batch_tiling(lbm_batch* b) {
   long long columns = 0, resident = 0;
   int dev = 0;
@@ -607,7 +610,7 @@ static void batch_tiling(lbm_batch* b) {
     resident = std::max<long long>(resident, step_resident_blocks((int)c->p.storage, c->tx, c->ty, dev));
   }
   for (lbm_ctx* c : b->c)
-    if (c->zchunk < 1) c->zchunk = columns >= resident ? c->geo.nz : auto_zchunk(c);
+    if (c->zchunk < 1) c->zchunk = columns >= resident ? std::min(c->geo.nz, kBatchChunk) : auto_zchunk(c);
 }
 
 static lbm_status build_groups(lbm_batch* b) {
