@@ -31,16 +31,20 @@ constexpr int kTapOff[27][3] = {
     {1, -1, -1},  {1, -1, 0},  {1, -1, 1},  {1, 0, -1},  {1, 0, 0},  {1, 0, 1},  {1, 1, -1},  {1, 1, 0},  {1, 1, 1}};
 
 // ---------------------------------------------------------------- forward convolution
-// grid (ceil(nvox / 128), cout / 32), 256 threads: wave w of block b owns voxels
-// [(4 b + w) 32, +32) and output channels [32 blockIdx.y, +32).
+// grid (ceil(nvox / 128), cout / (32 NT)), 256 threads: wave w of block b owns voxels
+// [(4 b + w) 32, +32) and output channels [32 NT blockIdx.y, +32 NT).  CIN is the input
+// channel count (a template constant, so the loads of a tap are issued ahead of its MFMAs);
+// the A fragment of a tap is reused for the NT output-channel tiles.
+template <int CIN, int NT>
 __global__ void __launch_bounds__(256) conv_fwd_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias, uint16_t* __restrict__ out,
-                                                       float* __restrict__ out_f32, int D, int H, int W, int cin,
-                                                       int cout, int relu, long long nvox) {
+                                                       float* __restrict__ out_f32, int D, int H, int W, int cout,
+                                                       int relu, long long nvox) {
+  constexpr int KS = CIN / 8;  // MFMA K steps per tap
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long v0 = ((long long)blockIdx.x * 4 + wave) * 32;
   if (v0 >= nvox) return;  // the whole wave leaves; the kernel has no barrier
-  const int co0 = blockIdx.y * 32;
+  const int co0 = blockIdx.y * 32 * NT;
   const long long va = v0 + (lane & 31);
   const bool valid = va < nvox;
   int x = 0, y = 0, z = 0;
@@ -55,34 +59,59 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const uint16_t* __restric
     nb = t / D;
   }
   const int kq = (lane >> 5) * 4;
-  floatx16 acc = {};
+  floatx16 acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) acc[j] = floatx16{};
   for (int tap = 0; tap < 27; ++tap) {
     const int zz = z + kTapOff[tap][0], yy = y + kTapOff[tap][1], xx = x + kTapOff[tap][2];
     const bool inb = valid && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
     const long long src = inb ? ((nb * D + zz) * H + yy) * (long long)W + xx : 0;
-    const uint16_t* arow = in + src * cin + kq;
-    const uint16_t* brow = w + ((long long)tap * cout + co0 + (lane & 31)) * cin + kq;
-    for (int c0 = 0; c0 < cin; c0 += 8) {
-      bf16x4 a = {0, 0, 0, 0};
-      if (inb) a = *reinterpret_cast<const bf16x4*>(arow + c0);
-      const bf16x4 b = *reinterpret_cast<const bf16x4*>(brow + c0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
-  }
-  const int col = co0 + (lane & 31);
-  const float bb = bias ? bias[col] : 0.0f;
+    const uint16_t* arow = in + src * CIN + kq;
+    bf16x4 a[KS], b[NT][KS];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const long long v = v0 + (r / 4) * 8 + kq + (r & 3);
-    if (v < nvox) {
-      float val = acc[r] + bb;
-      if (relu) val = fmaxf(val, 0.0f);
-      if (out_f32)
-        out_f32[v * cout + col] = val;
-      else
-        out[v * cout + col] = f2bf(val);
+    for (int k = 0; k < KS; ++k) {
+      a[k] = bf16x4{0, 0, 0, 0};
+      if (inb) a[k] = *reinterpret_cast<const bf16x4*>(arow + 8 * k);
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const uint16_t* brow = w + ((long long)tap * cout + co0 + 32 * j + (lane & 31)) * CIN + kq;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) b[j][k] = *reinterpret_cast<const bf16x4*>(brow + 8 * k);
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[k], b[j][k], acc[j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int col = co0 + 32 * j + (lane & 31);
+    const float bb = bias ? bias[col] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const long long v = v0 + (r / 4) * 8 + kq + (r & 3);
+      if (v < nvox) {
+        float val = acc[j][r] + bb;
+        if (relu) val = fmaxf(val, 0.0f);
+        if (out_f32)
+          out_f32[v * cout + col] = val;
+        else
+          out[v * cout + col] = f2bf(val);
+      }
     }
   }
+}
+
+template <int CIN>
+void launch_conv(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, float* out_f32, int d, int h,
+                 int wd, int cout, int relu, long long nvox, hipStream_t s) {
+  if (cout % 64 == 0)
+    hipLaunchKernelGGL((conv_fwd_kernel<CIN, 2>), dim3((unsigned)((nvox + 127) / 128), cout / 64), dim3(256), 0, s, in,
+                       w, bias, out, out_f32, d, h, wd, cout, relu, nvox);
+  else
+    hipLaunchKernelGGL((conv_fwd_kernel<CIN, 1>), dim3((unsigned)((nvox + 127) / 128), cout / 32), dim3(256), 0, s, in,
+                       w, bias, out, out_f32, d, h, wd, cout, relu, nvox);
 }
 
 // w_t[tap'][ci][co] = w[26 - tap'][co][ci]
@@ -97,77 +126,173 @@ __global__ void flip_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict
 }
 
 // ---------------------------------------------------------------- weight gradient
-// dw[tap][co][ci] = sum_v dout[v][co] in[v + off(tap)][ci]: GEMM with M = cout, N = cin,
-// K = voxels.  The voxels are taken row by row (rows = (n, z, y), x fastest) in chunks of
-// whole rows; one wave per (chunk, tap, co tile, ci tile) steps through its rows 8 voxels
-// at a time, lane l holding voxels x0 + kq .. x0 + kq + 3.  Partial sums per chunk go to
-// scratch and are added in chunk order by chunk_sum_kernel.
-constexpr int kChunk = 16384;  // voxels per chunk (whole rows, at least one)
+// dw[tap][co][ci] = sum_v dout[v][co] in[v + off(tap)][ci]: per tap a GEMM with M = cout,
+// N = cin, K = voxels.  The voxels are walked as row segments of kSeg along x, ordered
+// (n, z, segment, y) with y fastest; block (c, tile) of three waves owns the (co, ci) tile of
+// 32 x 32 and the c-th of nchunks contiguous ranges of row segments.  Wave k accumulates
+// the nine taps with dz = k - 1.  Per segment the block stages dout^T [co][x] into LDS, and
+// wave k stages the source rows (z + dz, y') as in^T [ci][x] over x0 - 4 .. x0 + kSeg + 3;
+// the three rows y - 1, y, y + 1 live in a ring, so the next segment of the same column
+// stages only row y + 2.  The K order of an MFMA is free: lane half h takes voxels
+// x0 + 32 h + 4 s + j at step s, so each lane walks its 32 voxels four at a time and the
+// dx = -1, +1 operands are its aligned 8-byte words shifted by one element, the word
+// before or after coming from the previous or the next step.
+constexpr int kSeg = 64;            // voxels per row segment
+constexpr int kRsA = kSeg + 4;      // LDS row stride of dout^T (elements; 34 dwords)
+constexpr int kRowB = kSeg + 8;     // staged source row, x0 - 4 .. x0 + kSeg + 3
+constexpr int kRsB = kRowB + 4;     // LDS row stride of in^T (38 dwords)
+constexpr int kWgradBlocks = 768;   // three resident blocks on each of 256 compute units
 
-__host__ __device__ inline int rows_per_chunk(int W) { return W >= kChunk ? 1 : kChunk / W; }
+__host__ __device__ inline int nseg_of(int W) { return (W + kSeg - 1) / kSeg; }
 
-__global__ void __launch_bounds__(64) wgrad_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ dout,
-                                                   float* __restrict__ part, int D, int H, int W, int cin, int cout,
-                                                   int nrows, int ci_tiles) {
-  const int lane = threadIdx.x;
-  const int chunk = blockIdx.x, tap = blockIdx.y;
-  const int co0 = (blockIdx.z / ci_tiles) * 32, ci0 = (blockIdx.z % ci_tiles) * 32;
-  const int kq = (lane >> 5) * 4;
-  const int co = co0 + (lane & 31), ci = ci0 + (lane & 31);
-  const bool ci_ok = ci < cin;
-  const int dz = kTapOff[tap][0], dy = kTapOff[tap][1], dx = kTapOff[tap][2];
-  const int rpc = rows_per_chunk(W);
-  const int r0 = chunk * rpc, r1 = min(r0 + rpc, nrows);
-  floatx16 acc = {};
-  for (int row = r0; row < r1; ++row) {
-    const int y = row % H, z = (row / H) % D, nb = row / (H * D);
-    const int yy = y + dy, zz = z + dz;
-    const bool row_ok = ci_ok && yy >= 0 && yy < H && zz >= 0 && zz < D;
-    const long long orow = (long long)row * W;                      // first voxel of this row
-    const long long irow = ((long long)(nb * D + zz) * H + yy) * W;  // first voxel of the source row
-    for (int x0 = 0; x0 < W; x0 += 8) {
-      bf16x4 a, b;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int x = x0 + kq + j, xx = x + dx;
-        uint16_t av = 0, bv = 0;
-        if (x < W) {
-          av = dout[(orow + x) * cout + co];
-          if (row_ok && xx >= 0 && xx < W) bv = in[(irow + xx) * cin + ci];
-        }
-        a[j] = (short)av;
-        b[j] = (short)bv;
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
-  }
-  // acc row m = co0 + 8 (r/4) + kq + r%4, column n = ci0 + lane % 32
-  float* dst = part + (long long)chunk * 27 * cout * cin + (long long)tap * cout * cin;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int m = co0 + (r / 4) * 8 + kq + (r & 3);
-    if (ci_ok) dst[(long long)m * cin + ci] = acc[r];
-  }
+struct WgradPlan {
+  long long nsr;  // row segments
+  int nchunks, ci_tiles, tiles;
+};
+
+inline WgradPlan wgrad_plan(int n, int d, int h, int wd, int cin, int cout) {
+  WgradPlan p;
+  p.nsr = (long long)n * d * h * nseg_of(wd);
+  p.ci_tiles = (cin + 31) / 32;
+  p.tiles = (cout / 32) * p.ci_tiles;
+  const long long want = (kWgradBlocks + p.tiles - 1) / p.tiles;
+  p.nchunks = (int)(want < p.nsr ? want : p.nsr);
+  if (p.nchunks < 1) p.nchunks = 1;
+  return p;
 }
 
-// dbias partials: block = chunk of rows, thread t sums channel t % cout over its voxels.
-__global__ void __launch_bounds__(256) bias_part_kernel(const uint16_t* __restrict__ dout, float* __restrict__ part,
-                                                        int cout, int W, int nrows) {
-  __shared__ float s[256];
-  const int t = threadIdx.x;
-  const int P = 256 / cout;
-  const int c = t % cout, p = t / cout;
-  const int rpc = rows_per_chunk(W);
-  const long long vbeg = (long long)blockIdx.x * rpc * W, vend = (long long)min(blockIdx.x * rpc + rpc, nrows) * W;
-  float acc = 0.0f;
-  if (p < P)
-    for (long long v = vbeg + p; v < vend; v += P) acc += bf2f(dout[v * cout + c]);
-  s[t] = acc;
-  __syncthreads();
-  if (t < cout) {
-    float sum = 0.0f;
-    for (int q = 0; q < P; ++q) sum += s[q * cout + t];
-    part[(long long)blockIdx.x * cout + t] = sum;
+__device__ __forceinline__ bf16x4 as_bf16x4(uint64_t u) { return __builtin_bit_cast(bf16x4, u); }
+
+__global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ dout,
+                                                       float* __restrict__ part, float* __restrict__ bpart, int D, int H,
+                                                       int W, int cin, int cout, long long nsr, int nchunks,
+                                                       int ci_tiles) {
+  __shared__ __align__(16) uint16_t sA[32 * kRsA];
+  __shared__ __align__(16) uint16_t sB[3][3][32 * kRsB];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, dz = wave - 1;
+  const int chunk = blockIdx.x;
+  const int co0 = (blockIdx.y / ci_tiles) * 32, ci0 = (blockIdx.y % ci_tiles) * 32;
+  const long long r0 = nsr * chunk / nchunks, r1 = nsr * (chunk + 1) / nchunks;
+  const int nseg = nseg_of(W);
+  const bool do_bias = bpart != nullptr && ci0 == 0;
+
+  floatx16 acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = floatx16{};
+  float bsum[2][8];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) bsum[k][i] = 0.0f;
+
+  long long prev_col = -1;
+  int prev_y = -2;
+  for (long long r = r0; r < r1; ++r) {
+    const int y = (int)(r % H);
+    const long long col = r / H;  // (n D + z) nseg + seg
+    const int seg = (int)(col % nseg);
+    const long long nz = col / nseg;  // n D + z
+    const int z = (int)(nz % D);
+    const int x0 = seg * kSeg;
+    const bool cont = col == prev_col && y == prev_y + 1;
+    prev_col = col;
+    prev_y = y;
+    __syncthreads();  // the previous segment's reads of LDS are done
+
+    // dout^T of row (nz, y): item it -> voxel x0 + it / 4, channels co0 + 8 (it % 4) + 0..7
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = t + 192 * k;
+      if (it < 256) {
+        const int q = it & 3, xi = it >> 2, x = x0 + xi;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (x < W) v = *reinterpret_cast<const uint4*>(dout + ((nz * H + y) * (long long)W + x) * cout + co0 + 8 * q);
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint16_t e = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
+          sA[(8 * q + i) * kRsA + xi] = e;
+          if (do_bias) bsum[k][i] += bf2f(e);
+        }
+      }
+    }
+    // in^T of the source rows (z + dz, yy) this wave needs: yy = y + 1 when the segment
+    // continues the previous one's column, else y - 1, y, y + 1
+    const int zz = z + dz;
+    for (int yy = cont ? y + 1 : y - 1; yy <= y + 1; ++yy) {
+      const bool row_ok = zz >= 0 && zz < D && yy >= 0 && yy < H;
+      const long long base = ((nz + dz) * H + yy) * (long long)W;
+      uint16_t* dst = sB[wave][(yy + 3) % 3];
+      for (int it = lane; it < 4 * kRowB; it += 64) {
+        const int q = it & 3, xi = it >> 2, x = x0 - 4 + xi;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (row_ok && x >= 0 && x < W && ci0 + 8 * q < cin)
+          v = *reinterpret_cast<const uint4*>(in + (base + x) * cin + ci0 + 8 * q);
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[(8 * q + i) * kRsB + xi] = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
+      }
+    }
+    __syncthreads();
+
+    const int h = lane >> 5, c = lane & 31;
+    const uint16_t* pa = sA + c * kRsA + 32 * h;
+    const uint16_t* pb[3];
+    uint64_t prv[3], cur[3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      pb[dy] = sB[wave][(y + dy + 2) % 3] + c * kRsB + 32 * h;
+      prv[dy] = *reinterpret_cast<const uint64_t*>(pb[dy]);
+      cur[dy] = *reinterpret_cast<const uint64_t*>(pb[dy] + 4);
+    }
+#pragma unroll
+    for (int st = 0; st < kSeg / 8; ++st) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(pa + 4 * st);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const uint64_t nxt = *reinterpret_cast<const uint64_t*>(pb[dy] + 8 + 4 * st);
+        const uint64_t bm = (cur[dy] << 16) | (prv[dy] >> 48);  // voxels x - 1 .. x + 2
+        const uint64_t bp = (cur[dy] >> 16) | (nxt << 48);      // voxels x + 1 .. x + 4
+        acc[3 * dy + 0] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, as_bf16x4(bm), acc[3 * dy + 0], 0, 0, 0);
+        acc[3 * dy + 1] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, as_bf16x4(cur[dy]), acc[3 * dy + 1], 0, 0, 0);
+        acc[3 * dy + 2] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, as_bf16x4(bp), acc[3 * dy + 2], 0, 0, 0);
+        prv[dy] = cur[dy];
+        cur[dy] = nxt;
+      }
+    }
+  }
+
+  // acc[3 dy + dx] row m = 8 (r / 4) + 4 h + r % 4 (co0 + m), column ci0 + lane % 32
+  {
+    const int h = lane >> 5, ci = ci0 + (lane & 31);
+    if (ci < cin) {
+      float* dst = part + ((long long)chunk * 27 + 9 * wave) * cout * cin;
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int co = co0 + (r / 4) * 8 + 4 * h + (r & 3);
+          dst[((long long)k * cout + co) * cin + ci] = acc[k][r];
+        }
+    }
+  }
+  if (do_bias) {
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(&sB[0][0][0]);  // [256 items][8]
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = t + 192 * k;
+      if (it < 256)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[it * 8 + i] = bsum[k][i];
+    }
+    __syncthreads();
+    if (t < 32) {
+      const int q = t >> 3, i = t & 7;
+      float sum = 0.0f;
+      for (int xi = 0; xi < kSeg; ++xi) sum += red[(xi * 4 + q) * 8 + i];
+      bpart[(long long)chunk * cout + co0 + t] = sum;
+    }
   }
 }
 
@@ -175,6 +300,7 @@ __global__ void chunk_sum_kernel(const float* __restrict__ part, float* __restri
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
   float s = 0.0f;
+#pragma unroll 8
   for (int k = 0; k < nchunks; ++k) s += part[(long long)k * len + i];
   out[i] = s;
 }
@@ -329,8 +455,14 @@ extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const floa
       (!out && !out_f32))
     return -1;
   const long long nvox = (long long)n * d * h * wd;
-  hipLaunchKernelGGL(conv_fwd_kernel, dim3(blocks(nvox, 128), cout / 32), dim3(256), 0, S(stream), in, w, bias, out,
-                     out_f32, d, h, wd, cin, cout, relu, nvox);
+  switch (cin) {
+    case 8: launch_conv<8>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    case 16: launch_conv<16>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    case 32: launch_conv<32>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    case 64: launch_conv<64>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    case 128: launch_conv<128>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    default: return -1;
+  }
   return done();
 }
 
@@ -348,33 +480,27 @@ extern "C" int surr_conv3d_dgrad(const uint16_t* dout, const uint16_t* w_t, uint
 }
 
 extern "C" size_t surr_conv3d_wgrad_scratch_bytes(int n, int d, int h, int wd, int cin, int cout) {
-  if (n < 1 || d < 1 || h < 1 || wd < 1 || cin < 1 || cout < 1) return 0;
-  const long long nrows = (long long)n * d * h;
-  const long long nchunks = (nrows + rows_per_chunk(wd) - 1) / rows_per_chunk(wd);
-  return (size_t)nchunks * ((size_t)27 * cout * cin + (size_t)cout) * sizeof(float);
+  if (n < 1 || d < 1 || h < 1 || wd < 1 || cin < 8 || cout < 32) return 0;
+  const WgradPlan p = wgrad_plan(n, d, h, wd, cin, cout);
+  return (size_t)p.nchunks * ((size_t)27 * cout * cin + (size_t)cout) * sizeof(float);
 }
 
 extern "C" int surr_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float* dw, float* dbias, void* scratch, int n,
                                  int d, int h, int wd, int cin, int cout, void* stream) {
-  if (n < 1 || d < 1 || h < 1 || wd < 1 || cin < 8 || cin % 8 || cout < 32 || cout % 32 || cout > 256 || !in ||
-      !dout || !dw || !scratch)
+  if (n < 1 || d < 1 || h < 1 || wd < 1 || cin < 8 || cin % 8 || cout < 32 || cout % 32 || !in || !dout || !dw ||
+      !scratch)
     return -1;
-  const long long nrows_ll = (long long)n * d * h;
-  if (nrows_ll * wd >= (1LL << 31)) return -1;
-  const int nrows = (int)nrows_ll;
-  const int nchunks = (nrows + rows_per_chunk(wd) - 1) / rows_per_chunk(wd);
-  const int ci_tiles = (cin + 31) / 32;
+  if ((long long)n * d * h * wd >= (1LL << 40)) return -1;
+  const WgradPlan p = wgrad_plan(n, d, h, wd, cin, cout);
   float* part = static_cast<float*>(scratch);
-  float* bpart = part + (size_t)nchunks * 27 * cout * cin;
-  hipLaunchKernelGGL(wgrad_kernel, dim3(nchunks, 27, (cout / 32) * ci_tiles), dim3(64), 0, S(stream), in, dout, part, d,
-                     h, wd, cin, cout, nrows, ci_tiles);
+  float* bpart = part + (size_t)p.nchunks * 27 * cout * cin;
+  hipLaunchKernelGGL(wgrad_kernel, dim3(p.nchunks, p.tiles), dim3(192), 0, S(stream), in, dout, part,
+                     dbias ? bpart : nullptr, d, h, wd, cin, cout, p.nsr, p.nchunks, p.ci_tiles);
   const long long len = 27LL * cout * cin;
-  hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(len, 256)), dim3(256), 0, S(stream), part, dw, len, nchunks);
-  if (dbias) {
-    hipLaunchKernelGGL(bias_part_kernel, dim3(nchunks), dim3(256), 0, S(stream), dout, bpart, cout, wd, nrows);
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(len, 256)), dim3(256), 0, S(stream), part, dw, len, p.nchunks);
+  if (dbias)
     hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(cout, 256)), dim3(256), 0, S(stream), bpart, dbias,
-                       (long long)cout, nchunks);
-  }
+                       (long long)cout, p.nchunks);
   return done();
 }
 

@@ -86,6 +86,30 @@ def test_conv_operators_against_reference(cin, cout):
     assert e_fwd < 1e-5 and e_wg < 1e-5 and e_bg < 1e-5
 
 
+def test_weight_gradient_long_ranges_against_reference():
+    """Weight and bias gradients where each block walks several row segments (the ring of
+    source rows carries over between consecutive y), the rows are ragged against the 64-voxel
+    segment (w = 70), the input channels fill a partial tile (cin = 40) and cout spans two
+    tiles."""
+    import torch
+    rng = np.random.default_rng(5)
+    n, d, h, w, cin, cout = 1, 4, 200, 70, 40, 64
+    x = bf16_round(rng.normal(size=(n, d, h, w, cin)))
+    dout = bf16_round(rng.normal(size=(n, d, h, w, cout)))
+    L = S._lib()
+    xd, doutd = to_dev_bf16(x), to_dev_bf16(dout)
+    gw = torch.empty((27, cout, cin), dtype=torch.float32, device="cuda")
+    gb = torch.empty(cout, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(L.surr_conv3d_wgrad_scratch_bytes(n, d, h, w, cin, cout) // 4 + 1, dtype=torch.float32,
+                          device="cuda")
+    assert L.surr_conv3d_wgrad(S._p(xd), S._p(doutd), S._p(gw), S._p(gb), S._p(scratch), n, d, h, w, cin, cout,
+                               None) == 0
+    rw, rb = R.conv3d_wgrad(x, dout)
+    e_wg, e_bg = rel(gw.cpu().numpy(), rw), rel(gb.cpu().numpy(), rb)
+    log(f"[wgrad {n}x{d}x{h}x{w} {cin}->{cout}] wgrad {e_wg:.2e} bgrad {e_bg:.2e}")
+    assert e_wg < 1e-5 and e_bg < 1e-5
+
+
 def test_network_gradients_against_reference():
     rng = np.random.default_rng(7)
     n, d, h, w = 2, 8, 8, 16
