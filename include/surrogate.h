@@ -48,7 +48,8 @@ int surr_relu_bwd(const uint16_t *y, const uint16_t *dy, uint16_t *dx, long long
  * gradient; (d, h, w) are the dimensions of the fine tensor (in, din).  Nearest 2x
  * upsampling with an added skip tensor, out = up(in) + skip, and its gradient with respect to
  * in (the gradient of skip is dout itself); (d, h, w) are the dimensions of the coarse tensor
- * (in, din), out and skip being 2d x 2h x 2w. */
+ * (in, din), out and skip being 2d x 2h x 2w.  c a multiple of 8 and every pointer 16-byte
+ * aligned (8 channels move per access), else -1. */
 int surr_pool_fwd(const uint16_t *in, uint16_t *out, int n, int d, int h, int wd, int c, void *stream);
 int surr_pool_bwd(const uint16_t *dout, uint16_t *din, int n, int d, int h, int wd, int c, void *stream);
 int surr_up_add_fwd(const uint16_t *in, const uint16_t *skip, uint16_t *out, int n, int d, int h, int wd, int c,
@@ -58,7 +59,8 @@ int surr_up_bwd(const uint16_t *dout, uint16_t *din, int n, int d, int h, int wd
 /* Mean-squared error over the first `used` of `stride` channels of pred (FP32) against
  * target (FP32, `used` channels): dpred = 2 (pred - target) / (count * used) written as
  * BF16 with zeros in the unused channels; the per-block partial sums of the squared error
- * go to loss_part (ceil(count / 256) floats), summed by the caller.  count voxels. */
+ * go to loss_part (ceil(count / 256) floats), summed by the caller.  count voxels; stride a
+ * multiple of 8 and dpred 16-byte aligned. */
 int surr_mse(const float *pred, const float *target, uint16_t *dpred, float *loss_part, long long count, int stride,
              int used, void *stream);
 
@@ -73,6 +75,10 @@ int surr_add(const uint16_t *a, const uint16_t *b, uint16_t *out, long long coun
 /* FP32 <-> BF16 conversion (round to nearest even). */
 int surr_to_bf16(const float *x, uint16_t *y, long long count, void *stream);
 int surr_to_f32(const uint16_t *x, float *y, long long count, void *stream);
+
+/* Network input: y[v][c] = bf16(x[v][c]) for c < c_src and 0 for c_src <= c < c_dst
+ * (x: [nvox][c_src] FP32, y: [nvox][c_dst] BF16). */
+int surr_pack_input(const float *x, uint16_t *y, long long nvox, int c_src, int c_dst, void *stream);
 
 #ifdef __cplusplus
 }

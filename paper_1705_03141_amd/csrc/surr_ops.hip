@@ -114,6 +114,149 @@ void launch_conv(const uint16_t* in, const uint16_t* w, const float* bias, uint1
                        w, bias, out, out_f32, d, h, wd, cout, relu, nvox);
 }
 
+// ---------------------------------------------------------------- forward convolution, staged
+// For cin in {16, 32}: a block of four waves owns a co tile of 32 and walks tiles of two
+// output rows x SEG voxels (grid-stride).  Per tile it stages into LDS every input voxel the
+// tile reads -- 3 z-planes x 4 rows x (SEG + 2) voxels, all cin channels, zeros outside the
+// volume -- with a voxel stride of cin + 4 elements (an odd number of 8-byte pairs of banks,
+// so the 32 voxels of an A fragment fall in distinct banks).  The K dimension of the GEMM,
+// 27 cin / 8 MFMA steps of (tap, 8 input channels), is split evenly over the waves; each wave
+// holds the weight fragments of its steps in registers for the whole kernel and accumulates
+// every M-tile of the output tile over them.  The four partial sums of an M-tile are added
+// in wave order through LDS by the wave that finalizes it (m % 4).
+template <int CIN>
+struct StagedConv {
+  static constexpr int SEG = CIN == 64 ? 32 : 64;  // voxels of an output row in a tile
+  static constexpr int XT = SEG / 32;              // M-tiles per output row
+  static constexpr int MT = 2 * XT;                // M-tiles per tile
+  static constexpr int RV = SEG + 2;               // staged voxels per row
+  static constexpr int VS = CIN + 4;               // staged voxel stride (elements)
+  static constexpr int SL = CIN / 8;               // 8-channel slices
+  static constexpr int KSTEPS = 27 * SL;
+  static constexpr int IPW = (KSTEPS + 3) / 4;     // K-steps of a wave, at most
+  static constexpr int STAGE_BYTES = 12 * RV * VS * 2;
+  static constexpr int RED_BYTES = 3 * MT * 4096;
+  static constexpr int LDS_BYTES = STAGE_BYTES > RED_BYTES ? STAGE_BYTES : RED_BYTES;
+  static_assert(LDS_BYTES <= 65536, "staged tile exceeds LDS");
+};
+
+template <int CIN>
+__global__ void __launch_bounds__(256, 2) conv_staged_kernel(const uint16_t* __restrict__ in,
+                                                             const uint16_t* __restrict__ w,
+                                                             const float* __restrict__ bias, uint16_t* __restrict__ out,
+                                                             float* __restrict__ out_f32, int D, int H, int W, int cout,
+                                                             int relu, long long ntiles) {
+  using P = StagedConv<CIN>;
+  __shared__ __align__(16) unsigned char lds[P::LDS_BYTES];
+  uint16_t* st = reinterpret_cast<uint16_t*>(lds);
+  float* red = reinterpret_cast<float*>(lds);
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, c = lane & 31;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int co0 = blockIdx.y * 32;
+  const int k0 = P::KSTEPS * wave / 4, nk = P::KSTEPS * (wave + 1) / 4 - k0;
+
+  bf16x4 wb[P::IPW];
+#pragma unroll
+  for (int i = 0; i < P::IPW; ++i) {
+    wb[i] = bf16x4{0, 0, 0, 0};
+    if (i < nk) {
+      const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
+      wb[i] = *reinterpret_cast<const bf16x4*>(w + ((long long)tap * cout + co0 + c) * CIN + sl * 8 + 4 * h);
+    }
+  }
+  const float bb = bias ? bias[co0 + c] : 0.0f;
+  const int lane_off = c * P::VS + 4 * h;
+  const int nseg = (W + P::SEG - 1) / P::SEG, nyp = (H + 1) / 2;
+
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int yp = (int)(tile % nyp);
+    const long long col = tile / nyp;  // (n D + z) nseg + seg
+    const int seg = (int)(col % nseg);
+    const long long nz = col / nseg;
+    const int z = (int)(nz % D);
+    const int x0 = seg * P::SEG, y0 = 2 * yp;
+
+    __syncthreads();  // the previous tile's reads of LDS are done
+    for (int it = t; it < 12 * P::RV * P::SL; it += 256) {
+      const int q = it % P::SL, v = (it / P::SL) % P::RV, row = it / (P::SL * P::RV);
+      const int dz = row / 4 - 1, ys = y0 + row % 4 - 1, zs = z + dz, x = x0 + v - 1;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (zs >= 0 && zs < D && ys >= 0 && ys < H && x >= 0 && x < W)
+        val = *reinterpret_cast<const uint4*>(in + (((nz + dz) * H + ys) * (long long)W + x) * CIN + 8 * q);
+      uint2* dst = reinterpret_cast<uint2*>(st + (row * P::RV + v) * P::VS + 8 * q);
+      dst[0] = make_uint2(val.x, val.y);
+      dst[1] = make_uint2(val.z, val.w);
+    }
+    __syncthreads();
+
+    floatx16 acc[P::MT];
+#pragma unroll
+    for (int m = 0; m < P::MT; ++m) acc[m] = floatx16{};
+#pragma unroll
+    for (int i = 0; i < P::IPW; ++i) {
+      if (i < nk) {
+        const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // each offset + 1
+        const uint16_t* a0 = st + ((dz * 4 + dy) * P::RV + dx) * P::VS + sl * 8 + lane_off;
+#pragma unroll
+        for (int m = 0; m < P::MT; ++m) {
+          const int moff = (m / P::XT) * P::RV * P::VS + (m % P::XT) * 32 * P::VS;
+          const bf16x4 a = *reinterpret_cast<const bf16x4*>(a0 + moff);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, wb[i], acc[m], 0, 0, 0);
+        }
+      }
+    }
+
+    __syncthreads();  // every wave is done with the staged rows; LDS now holds partial sums
+#pragma unroll
+    for (int m = 0; m < P::MT; ++m) {
+      const int f = m % 4;
+      if (wave != f) {
+        float* slot = red + (m * 3 + (wave < f ? wave : wave - 1)) * 1024;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) slot[r * 64 + lane] = acc[m][r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < P::MT; ++m) {
+      const int f = m % 4;
+      if (wave == f) {
+        const int y = y0 + m / P::XT, xb = x0 + (m % P::XT) * 32;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float sum = 0.0f;
+#pragma unroll
+          for (int ww = 0; ww < 4; ++ww)
+            sum += ww == f ? acc[m][r] : red[(m * 3 + (ww < f ? ww : ww - 1)) * 1024 + r * 64 + lane];
+          const int x = xb + (r / 4) * 8 + 4 * h + (r & 3);
+          if (x < W && y < H) {
+            float val = sum + bb;
+            if (relu) val = fmaxf(val, 0.0f);
+            const long long v = (nz * H + y) * (long long)W + x;
+            if (out_f32)
+              out_f32[v * cout + co0 + c] = val;
+            else
+              out[v * cout + co0 + c] = f2bf(val);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int CIN>
+void launch_staged(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, float* out_f32, int n,
+                   int d, int h, int wd, int cout, int relu, hipStream_t s) {
+  using P = StagedConv<CIN>;
+  const long long ntiles = (long long)n * d * ((wd + P::SEG - 1) / P::SEG) * ((h + 1) / 2);
+  const int ctiles = cout / 32;
+  const long long want = (512 + ctiles - 1) / ctiles;  // two resident blocks on each of 256 CUs
+  const unsigned gx = (unsigned)(ntiles < want ? ntiles : want);
+  hipLaunchKernelGGL(conv_staged_kernel<CIN>, dim3(gx, ctiles), dim3(256), 0, s, in, w, bias, out, out_f32, d, h, wd,
+                     cout, relu, ntiles);
+}
+
 // w_t[tap'][ci][co] = w[26 - tap'][co][ci]
 __global__ void flip_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int cin, int cout) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -296,94 +439,171 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
   }
 }
 
-__global__ void chunk_sum_kernel(const float* __restrict__ part, float* __restrict__ out, long long len, int nchunks) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+// out[i] = sum over k of part[k][i], i < len.  A block of 256 threads covers OPB outputs with
+// G = 256 / OPB groups; group g adds chunks g, g + G, ... in order, and the G group sums are
+// added in group order, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) chunk_sum_kernel(const float* __restrict__ part, float* __restrict__ out,
+                                                        long long len, int nchunks, int opb) {
+  __shared__ float sred[256];
+  const int t = threadIdx.x, o = t % opb, g = t / opb, G = 256 / opb;
+  const long long i = (long long)blockIdx.x * opb + o;
   float s = 0.0f;
-#pragma unroll 8
-  for (int k = 0; k < nchunks; ++k) s += part[(long long)k * len + i];
-  out[i] = s;
+  if (i < len) {
+#pragma unroll 4
+    for (int k = g; k < nchunks; k += G) s += part[(long long)k * len + i];
+  }
+  sred[t] = s;
+  __syncthreads();
+  if (g == 0 && i < len) {
+    float sum = 0.0f;
+    for (int q = 0; q < G; ++q) sum += sred[q * opb + o];
+    out[i] = sum;
+  }
+}
+
+inline void launch_chunk_sum(const float* part, float* out, long long len, int nchunks, hipStream_t s) {
+  const int opb = len >= 64 ? 64 : 32;
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)((len + opb - 1) / opb)), dim3(256), 0, s, part, out, len,
+                     nchunks, opb);
 }
 
 // ---------------------------------------------------------------- element-wise operators
-__global__ void relu_bwd_kernel(const uint16_t* __restrict__ y, const uint16_t* __restrict__ dy,
-                                uint16_t* __restrict__ dx, long long count) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) dx[i] = bf2f(y[i]) > 0.0f ? dy[i] : (uint16_t)0;
+// The element-wise operators move 8 channels (16 bytes) per thread; channel counts are
+// multiples of 8 wherever they are called with voxel layouts, and the flat operators take a
+// scalar tail.
+__device__ __forceinline__ void unpack8(uint4 u, float (&f)[8]) {
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f[2 * i] = __uint_as_float(w[i] << 16);
+    f[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+  }
 }
 
-// (d, h, w): dimensions of the fine lattice
+__device__ __forceinline__ uint4 pack8(const float (&f)[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ void relu_bwd_kernel(const uint16_t* __restrict__ y, const uint16_t* __restrict__ dy,
+                                uint16_t* __restrict__ dx, long long count, int vec) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long e = 8 * i;
+  if (vec && e + 8 <= count) {
+    const uint4 yv = *reinterpret_cast<const uint4*>(y + e), gv = *reinterpret_cast<const uint4*>(dy + e);
+    const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w}, gw[4] = {gv.x, gv.y, gv.z, gv.w};
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t lo = __uint_as_float(yw[k] << 16) > 0.0f ? 0x0000FFFFu : 0u;
+      const uint32_t hi = __uint_as_float(yw[k] & 0xFFFF0000u) > 0.0f ? 0xFFFF0000u : 0u;
+      o[k] = gw[k] & (lo | hi);
+    }
+    *reinterpret_cast<uint4*>(dx + e) = make_uint4(o[0], o[1], o[2], o[3]);
+  } else {
+    for (long long j = e; j < count && j < e + 8; ++j) dx[j] = bf2f(y[j]) > 0.0f ? dy[j] : (uint16_t)0;
+  }
+}
+
+// (d, h, w): dimensions of the fine lattice; thread = (coarse voxel, 8 channels)
 __global__ void pool_fwd_kernel(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int d, int h, int w, int c,
                                 long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const int ch = (int)(i % c);
-  long long t = i / c;
+  const int c8 = c / 8, ch = 8 * (int)(i % c8);
+  long long t = i / c8;
   const int x = (int)(t % (w / 2));
   t /= (w / 2);
   const int y = (int)(t % (h / 2));
   t /= (h / 2);
   const int z = (int)(t % (d / 2));
   const long long n = t / (d / 2);
-  float s = 0.0f;
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int k = 0; k < 8; ++k) {
     const int zz = 2 * z + (k >> 2), yy = 2 * y + ((k >> 1) & 1), xx = 2 * x + (k & 1);
-    s += bf2f(in[(((n * d + zz) * h + yy) * (long long)w + xx) * c + ch]);
+    float f[8];
+    unpack8(*reinterpret_cast<const uint4*>(in + (((n * d + zz) * h + yy) * (long long)w + xx) * c + ch), f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += f[j];
   }
-  out[i] = f2bf(0.125f * s);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] *= 0.125f;
+  *reinterpret_cast<uint4*>(out + (i / c8) * c + ch) = pack8(s);
 }
 
+// thread = (fine voxel, 8 channels)
 __global__ void pool_bwd_kernel(const uint16_t* __restrict__ dout, uint16_t* __restrict__ din, int d, int h, int w,
                                 int c, long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const int ch = (int)(i % c);
-  long long t = i / c;
+  const int c8 = c / 8, ch = 8 * (int)(i % c8);
+  long long t = i / c8;
+  const long long vf = t;
   const int x = (int)(t % w);
   t /= w;
   const int y = (int)(t % h);
   t /= h;
   const int z = (int)(t % d);
   const long long n = t / d;
-  const float g = bf2f(dout[(((n * (d / 2) + z / 2) * (h / 2) + y / 2) * (long long)(w / 2) + x / 2) * c + ch]);
-  din[i] = f2bf(0.125f * g);
+  float f[8];
+  unpack8(*reinterpret_cast<const uint4*>(dout + (((n * (d / 2) + z / 2) * (h / 2) + y / 2) * (long long)(w / 2) + x / 2) *
+                                                     c +
+                                                 ch),
+          f);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) f[j] *= 0.125f;
+  *reinterpret_cast<uint4*>(din + vf * c + ch) = pack8(f);
 }
 
-// (d, h, w): dimensions of the coarse input; out and skip are 2d x 2h x 2w
+// (d, h, w): dimensions of the coarse input; out and skip are 2d x 2h x 2w; thread = (fine
+// voxel, 8 channels)
 __global__ void up_add_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ skip,
                               uint16_t* __restrict__ out, int d, int h, int w, int c, long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const int ch = (int)(i % c);
-  long long t = i / c;
+  const int c8 = c / 8, ch = 8 * (int)(i % c8);
+  long long t = i / c8;
+  const long long vf = t;
   const int x = (int)(t % (2 * w));
   t /= (2 * w);
   const int y = (int)(t % (2 * h));
   t /= (2 * h);
   const int z = (int)(t % (2 * d));
   const long long n = t / (2 * d);
-  const float a = bf2f(in[(((n * d + z / 2) * h + y / 2) * (long long)w + x / 2) * c + ch]);
-  out[i] = f2bf(a + bf2f(skip[i]));
+  float a[8], b[8];
+  unpack8(*reinterpret_cast<const uint4*>(in + (((n * d + z / 2) * h + y / 2) * (long long)w + x / 2) * c + ch), a);
+  unpack8(*reinterpret_cast<const uint4*>(skip + vf * c + ch), b);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] += b[j];
+  *reinterpret_cast<uint4*>(out + vf * c + ch) = pack8(a);
 }
 
+// thread = (coarse voxel, 8 channels)
 __global__ void up_bwd_kernel(const uint16_t* __restrict__ dout, uint16_t* __restrict__ din, int d, int h, int w, int c,
                               long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const int ch = (int)(i % c);
-  long long t = i / c;
+  const int c8 = c / 8, ch = 8 * (int)(i % c8);
+  long long t = i / c8;
+  const long long vc = t;
   const int x = (int)(t % w);
   t /= w;
   const int y = (int)(t % h);
   t /= h;
   const int z = (int)(t % d);
   const long long n = t / d;
-  float s = 0.0f;
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int k = 0; k < 8; ++k) {
     const int zz = 2 * z + (k >> 2), yy = 2 * y + ((k >> 1) & 1), xx = 2 * x + (k & 1);
-    s += bf2f(dout[(((n * 2 * d + zz) * (2 * h) + yy) * (long long)(2 * w) + xx) * c + ch]);
+    float f[8];
+    unpack8(*reinterpret_cast<const uint4*>(dout + (((n * 2 * d + zz) * (2 * h) + yy) * (long long)(2 * w) + xx) * c + ch),
+            f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += f[j];
   }
-  din[i] = f2bf(s);
+  *reinterpret_cast<uint4*>(din + vc * c + ch) = pack8(s);
 }
 
 __global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
@@ -394,14 +614,18 @@ __global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ pred
   float e2 = 0.0f;
   if (v < count) {
     const float scale = 2.0f / ((float)count * (float)used);
-    for (int k = 0; k < stride; ++k) {
-      float g = 0.0f;
-      if (k < used) {
-        const float e = pred[v * stride + k] - target[v * used + k];
-        e2 += e * e;
-        g = scale * e;
+    for (int k0 = 0; k0 < stride; k0 += 8) {
+      float g[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        g[j] = 0.0f;
+        if (k0 + j < used) {
+          const float e = pred[v * stride + k0 + j] - target[v * used + k0 + j];
+          e2 += e * e;
+          g[j] = scale * e;
+        }
       }
-      dpred[v * stride + k] = f2bf(g);
+      *reinterpret_cast<uint4*>(dpred + v * stride + k0) = pack8(g);
     }
   }
   s[threadIdx.x] = e2;
@@ -427,15 +651,35 @@ __global__ void adam_kernel(float* __restrict__ w, uint16_t* __restrict__ wb, co
   wb[i] = f2bf(wi);
 }
 
-__global__ void add_kernel(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b, uint16_t* __restrict__ out,
-                           long long count) {
+// out may alias a or b: each thread reads its 8 elements before writing them
+__global__ void add_kernel(const uint16_t* a, const uint16_t* b, uint16_t* out, long long count, int vec) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) out[i] = f2bf(bf2f(a[i]) + bf2f(b[i]));
+  const long long e = 8 * i;
+  if (vec && e + 8 <= count) {
+    float fa[8], fb[8];
+    unpack8(*reinterpret_cast<const uint4*>(a + e), fa);
+    unpack8(*reinterpret_cast<const uint4*>(b + e), fb);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) fa[j] += fb[j];
+    *reinterpret_cast<uint4*>(out + e) = pack8(fa);
+  } else {
+    for (long long j = e; j < count && j < e + 8; ++j) out[j] = f2bf(bf2f(a[j]) + bf2f(b[j]));
+  }
 }
 
 __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) y[i] = f2bf(x[i]);
+}
+
+// y[v][c] = bf16(x[v][c]) for c < c_src, 0 for c_src <= c < c_dst
+__global__ void pack_input_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, long long count, int c_src,
+                                  int c_dst) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const long long v = i / c_dst;
+  const int c = (int)(i % c_dst);
+  y[i] = c < c_src ? f2bf(x[v * c_src + c]) : (uint16_t)0;
 }
 
 __global__ void to_f32_kernel(const uint16_t* __restrict__ x, float* __restrict__ y, long long count) {
@@ -445,6 +689,7 @@ __global__ void to_f32_kernel(const uint16_t* __restrict__ x, float* __restrict_
 
 inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 inline unsigned blocks(long long count, int per) { return (unsigned)((count + per - 1) / per); }
+inline bool aligned16(const void* p) { return p && ((uintptr_t)p & 15) == 0; }
 inline int done() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
 }  // namespace
@@ -457,8 +702,8 @@ extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const floa
   const long long nvox = (long long)n * d * h * wd;
   switch (cin) {
     case 8: launch_conv<8>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
-    case 16: launch_conv<16>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
-    case 32: launch_conv<32>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    case 16: launch_staged<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
+    case 32: launch_staged<32>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
     case 64: launch_conv<64>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
     case 128: launch_conv<128>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
     default: return -1;
@@ -496,53 +741,57 @@ extern "C" int surr_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float
   float* bpart = part + (size_t)p.nchunks * 27 * cout * cin;
   hipLaunchKernelGGL(wgrad_kernel, dim3(p.nchunks, p.tiles), dim3(192), 0, S(stream), in, dout, part,
                      dbias ? bpart : nullptr, d, h, wd, cin, cout, p.nsr, p.nchunks, p.ci_tiles);
-  const long long len = 27LL * cout * cin;
-  hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(len, 256)), dim3(256), 0, S(stream), part, dw, len, p.nchunks);
-  if (dbias)
-    hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(cout, 256)), dim3(256), 0, S(stream), bpart, dbias,
-                       (long long)cout, p.nchunks);
+  launch_chunk_sum(part, dw, 27LL * cout * cin, p.nchunks, S(stream));
+  if (dbias) launch_chunk_sum(bpart, dbias, (long long)cout, p.nchunks, S(stream));
   return done();
 }
 
 extern "C" int surr_relu_bwd(const uint16_t* y, const uint16_t* dy, uint16_t* dx, long long count, void* stream) {
   if (count < 0 || !y || !dy || !dx) return -1;
-  hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), y, dy, dx, count);
+  if (count == 0) return 0;
+  const int vec = aligned16(y) && aligned16(dy) && aligned16(dx);
+  hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks(count, 8 * 256)), dim3(256), 0, S(stream), y, dy, dx, count, vec);
   return done();
 }
 
 extern "C" int surr_pool_fwd(const uint16_t* in, uint16_t* out, int n, int d, int h, int wd, int c, void* stream) {
-  if (n < 1 || d < 2 || h < 2 || wd < 2 || (d | h | wd) & 1 || c < 1 || !in || !out) return -1;
-  const long long count = (long long)n * (d / 2) * (h / 2) * (wd / 2) * c;
+  if (n < 1 || d < 2 || h < 2 || wd < 2 || (d | h | wd) & 1 || c < 8 || c % 8 || !aligned16(in) || !aligned16(out))
+    return -1;
+  const long long count = (long long)n * (d / 2) * (h / 2) * (wd / 2) * (c / 8);
   hipLaunchKernelGGL(pool_fwd_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), in, out, d, h, wd, c, count);
   return done();
 }
 
 extern "C" int surr_pool_bwd(const uint16_t* dout, uint16_t* din, int n, int d, int h, int wd, int c, void* stream) {
-  if (n < 1 || d < 2 || h < 2 || wd < 2 || (d | h | wd) & 1 || c < 1 || !dout || !din) return -1;
-  const long long count = (long long)n * d * h * wd * c;
+  if (n < 1 || d < 2 || h < 2 || wd < 2 || (d | h | wd) & 1 || c < 8 || c % 8 || !aligned16(dout) || !aligned16(din))
+    return -1;
+  const long long count = (long long)n * d * h * wd * (c / 8);
   hipLaunchKernelGGL(pool_bwd_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), dout, din, d, h, wd, c, count);
   return done();
 }
 
 extern "C" int surr_up_add_fwd(const uint16_t* in, const uint16_t* skip, uint16_t* out, int n, int d, int h, int wd,
                                int c, void* stream) {
-  if (n < 1 || d < 1 || h < 1 || wd < 1 || c < 1 || !in || !skip || !out) return -1;
-  const long long count = (long long)n * 8 * d * h * wd * c;
+  if (n < 1 || d < 1 || h < 1 || wd < 1 || c < 8 || c % 8 || !aligned16(in) || !aligned16(skip) || !aligned16(out))
+    return -1;
+  const long long count = (long long)n * 8 * d * h * wd * (c / 8);
   hipLaunchKernelGGL(up_add_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), in, skip, out, d, h, wd, c,
                      count);
   return done();
 }
 
 extern "C" int surr_up_bwd(const uint16_t* dout, uint16_t* din, int n, int d, int h, int wd, int c, void* stream) {
-  if (n < 1 || d < 1 || h < 1 || wd < 1 || c < 1 || !dout || !din) return -1;
-  const long long count = (long long)n * d * h * wd * c;
+  if (n < 1 || d < 1 || h < 1 || wd < 1 || c < 8 || c % 8 || !aligned16(dout) || !aligned16(din)) return -1;
+  const long long count = (long long)n * d * h * wd * (c / 8);
   hipLaunchKernelGGL(up_bwd_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), dout, din, d, h, wd, c, count);
   return done();
 }
 
 extern "C" int surr_mse(const float* pred, const float* target, uint16_t* dpred, float* loss_part, long long count,
                         int stride, int used, void* stream) {
-  if (count < 1 || stride < 1 || used < 1 || used > stride || !pred || !target || !dpred || !loss_part) return -1;
+  if (count < 1 || stride < 8 || stride % 8 || used < 1 || used > stride || !pred || !target || !aligned16(dpred) ||
+      !loss_part)
+    return -1;
   hipLaunchKernelGGL(mse_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), pred, target, dpred, loss_part,
                      count, stride, used);
   return done();
@@ -559,7 +808,9 @@ extern "C" int surr_adam(float* w, uint16_t* w_bf16, const float* g, float* m, f
 
 extern "C" int surr_add(const uint16_t* a, const uint16_t* b, uint16_t* out, long long count, void* stream) {
   if (count < 0 || !a || !b || !out) return -1;
-  hipLaunchKernelGGL(add_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), a, b, out, count);
+  if (count == 0) return 0;
+  const int vec = aligned16(a) && aligned16(b) && aligned16(out);
+  hipLaunchKernelGGL(add_kernel, dim3(blocks(count, 8 * 256)), dim3(256), 0, S(stream), a, b, out, count, vec);
   return done();
 }
 
@@ -572,5 +823,13 @@ extern "C" int surr_to_bf16(const float* x, uint16_t* y, long long count, void* 
 extern "C" int surr_to_f32(const uint16_t* x, float* y, long long count, void* stream) {
   if (count < 0 || !x || !y) return -1;
   hipLaunchKernelGGL(to_f32_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), x, y, count);
+  return done();
+}
+
+extern "C" int surr_pack_input(const float* x, uint16_t* y, long long nvox, int c_src, int c_dst, void* stream) {
+  if (nvox < 0 || c_src < 1 || c_dst < c_src || !x || !y) return -1;
+  const long long count = nvox * c_dst;
+  if (count == 0) return 0;
+  hipLaunchKernelGGL(pack_input_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), x, y, count, c_src, c_dst);
   return done();
 }

@@ -56,6 +56,7 @@ def _lib():
         L.surr_add.argtypes = [vp, vp, vp, ll, vp]
         L.surr_to_bf16.argtypes = [vp, vp, ll, vp]
         L.surr_to_f32.argtypes = [vp, vp, ll, vp]
+        L.surr_pack_input.argtypes = [vp, vp, ll, i, i, vp]
         _bound = True
     return L
 
@@ -86,6 +87,7 @@ class Network:
         self.device = dev = device
         rng = np.random.default_rng(seed)
         self.w32, self.wbf, self.wt, self.b, self.gw, self.gb, self.m, self.v = {}, {}, {}, {}, {}, {}, {}, {}
+        self.bbf = {}
         for name, cin, cout in LAYERS:
             std = math.sqrt(2.0 / (27 * cin))
             w0 = rng.normal(0.0, std, size=(27, cout, cin)).astype(np.float32)
@@ -97,6 +99,7 @@ class Network:
             self.wt[name] = torch.empty((27, cin, cout), dtype=torch.int16, device=dev)
             self.gw[name] = torch.zeros((27, cout, cin), dtype=torch.float32, device=dev)
             self.gb[name] = torch.zeros(cout, dtype=torch.float32, device=dev)
+            self.bbf[name] = torch.empty(cout, dtype=torch.int16, device=dev)  # BF16 copy Adam writes (unused)
             for store in (self.m, self.v):
                 store[name] = (torch.zeros_like(self.w32[name]), torch.zeros_like(self.b[name]))
         self._refresh_bf16()
@@ -146,13 +149,22 @@ class Network:
         _ok(L.surr_conv3d_fwd(_p(src), _p(self.wbf[name]), _p(self.b[name]), _p(dst), _p(out_f32), *dims, cin, cout,
                               1 if relu else 0, self.stream), f"conv {name}")
 
-    def set_input(self, x: np.ndarray):
-        """x: (n, d, h, w, 4) host array."""
+    def _device_f32(self, a):
+        """A host array or a device tensor as a contiguous FP32 tensor on the network's device."""
         t = self.torch
-        full = np.zeros(self.shape + (IN_CH,), dtype=np.float32)
-        full[..., :FIELDS] = x
-        xf = t.from_numpy(full).to(self.device)
-        _ok(_lib().surr_to_bf16(_p(xf), _p(self.act["x"]), xf.numel(), self.stream), "input")
+        if isinstance(a, t.Tensor):
+            if a.device.type != t.device(self.device).type or a.dtype != t.float32:
+                raise TypeError("expected an FP32 tensor on the network's device")
+            return a.contiguous()
+        return t.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(self.device)
+
+    def set_input(self, x):
+        """x: (n, d, h, w, 4) host array or FP32 device tensor."""
+        xf = self._device_f32(x)
+        if tuple(xf.shape) != self.shape + (FIELDS,):
+            raise ValueError(f"input of shape {tuple(xf.shape)}, expected {self.shape + (FIELDS,)}")
+        nv = self.shape[0] * self.shape[1] * self.shape[2] * self.shape[3]
+        _ok(_lib().surr_pack_input(_p(xf), _p(self.act["x"]), nv, FIELDS, IN_CH, self.stream), "input")
 
     def forward(self):
         L = _lib()
@@ -224,13 +236,18 @@ class Network:
         self._relu_bwd(A["e1a"], g0, g1)
         self._wgrad(A["x"], g1, "e1a", full)
 
-    def loss_and_grad(self, target):
-        """target: (n, d, h, w, 4) FP32 device tensor.  Returns (loss, BF16 gradient)."""
+    def loss_and_grad(self, target, sync: bool = True):
+        """target: (n, d, h, w, 4) FP32 device tensor.  Returns (loss, BF16 gradient); with
+        sync=False the loss is left on the device (read it with last_loss) and None returned."""
         dy = self.g_full32[2]
         nv = self.shape[0] * self.shape[1] * self.shape[2] * self.shape[3]
         _ok(_lib().surr_mse(_p(self.y), _p(target), _p(dy), _p(self.loss_part), nv, 32, FIELDS, self.stream), "mse")
-        loss = float(self.loss_part.cpu().numpy().astype(np.float64).sum()) / (nv * FIELDS)
-        return loss, dy
+        return (self.last_loss() if sync else None), dy
+
+    def last_loss(self) -> float:
+        """Loss of the last loss_and_grad call (waits for it)."""
+        nv = self.shape[0] * self.shape[1] * self.shape[2] * self.shape[3]
+        return float(self.loss_part.cpu().numpy().astype(np.float64).sum()) / (nv * FIELDS)
 
     def adam_step(self, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1
@@ -240,16 +257,16 @@ class Network:
             vw, vb = self.v[name]
             _ok(L.surr_adam(_p(self.w32[name]), _p(self.wbf[name]), _p(self.gw[name]), _p(mw), _p(vw),
                             self.w32[name].numel(), self.lr, beta1, beta2, eps, self.t, self.stream), "adam w")
-            bb = self.torch.empty(cout, dtype=self.torch.int16, device=self.device)
-            _ok(L.surr_adam(_p(self.b[name]), _p(bb), _p(self.gb[name]), _p(mb), _p(vb), cout, self.lr, beta1, beta2,
+            _ok(L.surr_adam(_p(self.b[name]), _p(self.bbf[name]), _p(self.gb[name]), _p(mb), _p(vb), cout, self.lr, beta1, beta2,
                             eps, self.t, self.stream), "adam b")
             _ok(L.surr_conv3d_flip_weights(_p(self.wbf[name]), _p(self.wt[name]), cin, cout, self.stream), "flip")
 
-    def train_step(self, x: np.ndarray, target: np.ndarray) -> float:
+    def train_step(self, x, target, sync_loss: bool = True):
+        """One forward, backward and Adam step on (x, target): host arrays or FP32 device
+        tensors of shape (n, d, h, w, 4).  Returns the loss (None with sync_loss=False)."""
         self.set_input(x)
         self.forward()
-        tgt = self.torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32)).to(self.device)
-        loss, dy = self.loss_and_grad(tgt)
+        loss, dy = self.loss_and_grad(self._device_f32(target), sync=sync_loss)
         self.backward(dy)
         self.adam_step()
         return loss

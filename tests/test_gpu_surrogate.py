@@ -86,6 +86,30 @@ def test_conv_operators_against_reference(cin, cout):
     assert e_fwd < 1e-5 and e_wg < 1e-5 and e_bg < 1e-5
 
 
+@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 64)])
+def test_forward_many_tiles_against_reference(cin, cout):
+    """Forward convolution where blocks walk several tiles, h is odd (the last tile's second
+    row is outside the volume) and w = 70 is ragged against the tile width."""
+    import torch
+    rng = np.random.default_rng(cin * cout)
+    n, d, h, w = 1, 8, 41, 70
+    x = bf16_round(rng.normal(size=(n, d, h, w, cin)))
+    wt = bf16_round(rng.normal(size=(27, cout, cin)) * 0.1)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    L = S._lib()
+    xd, wd = to_dev_bf16(x), to_dev_bf16(wt)
+    bd = torch.from_numpy(b.astype(np.float32)).to("cuda")
+    y32 = torch.empty((n, d, h, w, cout), dtype=torch.float32, device="cuda")
+    assert L.surr_conv3d_fwd(S._p(xd), S._p(wd), S._p(bd), None, S._p(y32), n, d, h, w, cin, cout, 0, None) == 0
+    ref = R.conv3d(x, wt, b)
+    e_fwd = rel(y32.cpu().numpy(), ref)
+    yb = torch.empty((n, d, h, w, cout), dtype=torch.int16, device="cuda")
+    assert L.surr_conv3d_fwd(S._p(xd), S._p(wd), S._p(bd), S._p(yb), None, n, d, h, w, cin, cout, 1, None) == 0
+    e_relu = rel(from_dev_bf16(yb), bf16_round(np.maximum(ref, 0.0)))
+    log(f"[conv {n}x{d}x{h}x{w} {cin}->{cout}] fwd {e_fwd:.2e} relu/bf16 {e_relu:.2e}")
+    assert e_fwd < 1e-5 and e_relu < 1e-2
+
+
 def test_weight_gradient_long_ranges_against_reference():
     """Weight and bias gradients where each block walks several row segments (the ring of
     source rows carries over between consecutive y), the rows are ragged against the 64-voxel
@@ -108,6 +132,63 @@ def test_weight_gradient_long_ranges_against_reference():
     e_wg, e_bg = rel(gw.cpu().numpy(), rw), rel(gb.cpu().numpy(), rb)
     log(f"[wgrad {n}x{d}x{h}x{w} {cin}->{cout}] wgrad {e_wg:.2e} bgrad {e_bg:.2e}")
     assert e_wg < 1e-5 and e_bg < 1e-5
+
+
+def test_elementwise_operators_against_reference():
+    """Pooling, upsampling, ReLU gradient, addition, input packing and the squared error
+    against the FP64 reference: each output is the reference value rounded once to BF16 (the
+    sums of BF16 inputs are exact in FP32 here, up to 8 terms of equal exponent range)."""
+    import torch
+    rng = np.random.default_rng(11)
+    L = S._lib()
+    n, d, h, w, c = 2, 4, 6, 10, 40
+    fine = bf16_round(rng.normal(size=(n, d, h, w, c)))
+    coarse = bf16_round(rng.normal(size=(n, d // 2, h // 2, w // 2, c)))
+    fd, cd = to_dev_bf16(fine), to_dev_bf16(coarse)
+    out_c = torch.empty_like(cd)
+    assert L.surr_pool_fwd(S._p(fd), S._p(out_c), n, d, h, w, c, None) == 0
+    assert rel(from_dev_bf16(out_c), bf16_round(R.pool(fine))) < 4e-3
+    out_f = torch.empty_like(fd)
+    assert L.surr_pool_bwd(S._p(cd), S._p(out_f), n, d, h, w, c, None) == 0
+    assert np.array_equal(from_dev_bf16(out_f), bf16_round(R.pool_bwd(coarse)))
+    assert L.surr_up_add_fwd(S._p(cd), S._p(fd), S._p(out_f), n, d // 2, h // 2, w // 2, c, None) == 0
+    assert rel(from_dev_bf16(out_f), bf16_round(R.up(coarse) + fine)) < 4e-3
+    assert L.surr_up_bwd(S._p(fd), S._p(out_c), n, d // 2, h // 2, w // 2, c, None) == 0
+    assert rel(from_dev_bf16(out_c), bf16_round(R.up_bwd(fine))) < 4e-3
+    assert L.surr_pool_fwd(S._p(fd), S._p(out_c), n, d, h, w, 12, None) == -1  # channels not a multiple of 8
+    # flat operators: a ragged count, then a pointer off the 16-byte grid (scalar path)
+    count = fine.size - 5
+    y, g = fine.ravel(), coarse.ravel()
+    gd = to_dev_bf16(np.resize(g, fine.size))
+    dx = torch.zeros_like(fd)
+    assert L.surr_relu_bwd(S._p(fd), S._p(gd), S._p(dx), count, None) == 0
+    want = np.where(y > 0, np.resize(g, fine.size), 0.0)
+    got = from_dev_bf16(dx).ravel()
+    assert np.array_equal(got[:count], want[:count]) and not got[count:].any()
+    flat_a, flat_b = fd.view(-1), gd.view(-1)
+    o = torch.zeros_like(flat_a)
+    assert L.surr_add(S._p(flat_a[1:]), S._p(flat_b[1:]), S._p(o[1:]), count, None) == 0
+    ref = bf16_round(y[1:count + 1] + np.resize(g, fine.size)[1:count + 1])
+    got = from_dev_bf16(o)
+    assert rel(got[1:count + 1], ref) < 4e-3 and got[0] == 0 and not got[count + 1:].any()
+    # input packing and the squared error
+    nv = n * d * h * w
+    x4 = rng.normal(size=(nv, 4)).astype(np.float32)
+    packed = torch.empty((nv, 8), dtype=torch.int16, device="cuda")
+    assert L.surr_pack_input(S._p(torch.from_numpy(x4).cuda()), S._p(packed), nv, 4, 8, None) == 0
+    pk = from_dev_bf16(packed)
+    assert np.array_equal(pk[:, :4], bf16_round(x4)) and not pk[:, 4:].any()
+    pred = rng.normal(size=(nv, 32)).astype(np.float32)
+    tgt = rng.normal(size=(nv, 4)).astype(np.float32)
+    dp = torch.empty((nv, 32), dtype=torch.int16, device="cuda")
+    part = torch.empty((nv + 255) // 256, dtype=torch.float32, device="cuda")
+    assert L.surr_mse(S._p(torch.from_numpy(pred).cuda()), S._p(torch.from_numpy(tgt).cuda()), S._p(dp), S._p(part),
+                      nv, 32, 4, None) == 0
+    loss_ref, g_ref = R.mse(pred.astype(np.float64), tgt.astype(np.float64))
+    loss = float(part.cpu().numpy().astype(np.float64).sum()) / (nv * 4)
+    assert abs(loss - loss_ref) / loss_ref < 1e-4
+    assert rel(from_dev_bf16(dp), g_ref) < 4e-3 and not from_dev_bf16(dp)[:, 4:].any()
+    log(f"[element-wise] pool/up/relu/add/pack/mse match; loss {loss:.6e} ref {loss_ref:.6e}")
 
 
 def test_network_gradients_against_reference():

@@ -149,6 +149,14 @@ class StandIn:
         _store_bf16(y, x.numpy().astype(np.float64).ravel()[:count])
         return 0
 
+    def surr_pack_input(self, x, y, nvox, c_src, c_dst, stream):
+        _need(x, nvox * c_src, "pack x")
+        _need(y, nvox * c_dst, "pack y")
+        v = np.zeros((nvox, c_dst))
+        v[:, :c_src] = x.numpy().astype(np.float64).reshape(-1)[: nvox * c_src].reshape(nvox, c_src)
+        _store_bf16(y, v)
+        return 0
+
     def surr_to_f32(self, x, y, count, stream):
         y.view(-1)[:count].copy_(torch.from_numpy(_f32_of_bf16(x)[:count].astype(np.float32)))
         return 0
