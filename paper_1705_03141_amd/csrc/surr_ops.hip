@@ -115,15 +115,16 @@ void launch_conv(const uint16_t* in, const uint16_t* w, const float* bias, uint1
 }
 
 // ---------------------------------------------------------------- forward convolution, staged
-// For cin in {16, 32}: a block of four waves owns a co tile of 32 and walks tiles of two
+// For cin in {16, 32, 64}: a block of NW waves owns a co tile of 32 and walks tiles of two
 // output rows x SEG voxels (grid-stride).  Per tile it stages into LDS every input voxel the
 // tile reads -- 3 z-planes x 4 rows x (SEG + 2) voxels, all cin channels, zeros outside the
 // volume -- with a voxel stride of cin + 4 elements (an odd number of 8-byte pairs of banks,
 // so the 32 voxels of an A fragment fall in distinct banks).  The K dimension of the GEMM,
 // 27 cin / 8 MFMA steps of (tap, 8 input channels), is split evenly over the waves; each wave
 // holds the weight fragments of its steps in registers for the whole kernel and accumulates
-// every M-tile of the output tile over them.  The four partial sums of an M-tile are added
-// in wave order through LDS by the wave that finalizes it (m % 4).
+// every M-tile of the output tile over them.  The NW partial sums of an M-tile are added in
+// wave order through LDS by the wave that finalizes it (m % NW).  NW = 8 for 64 channels
+// keeps a wave's weight fragments at 54 registers.
 template <int CIN>
 struct StagedConv {
   static constexpr int SEG = CIN == 64 ? 32 : 64;  // voxels of an output row in a tile
@@ -132,16 +133,17 @@ struct StagedConv {
   static constexpr int RV = SEG + 2;               // staged voxels per row
   static constexpr int VS = CIN + 4;               // staged voxel stride (elements)
   static constexpr int SL = CIN / 8;               // 8-channel slices
+  static constexpr int NW = CIN == 64 ? 8 : 4;     // waves per block
   static constexpr int KSTEPS = 27 * SL;
-  static constexpr int IPW = (KSTEPS + 3) / 4;     // K-steps of a wave, at most
+  static constexpr int IPW = (KSTEPS + NW - 1) / NW;  // K-steps of a wave, at most
   static constexpr int STAGE_BYTES = 12 * RV * VS * 2;
-  static constexpr int RED_BYTES = 3 * MT * 4096;
+  static constexpr int RED_BYTES = (NW - 1) * MT * 4096;
   static constexpr int LDS_BYTES = STAGE_BYTES > RED_BYTES ? STAGE_BYTES : RED_BYTES;
   static_assert(LDS_BYTES <= 65536, "staged tile exceeds LDS");
 };
 
 template <int CIN>
-__global__ void __launch_bounds__(256, 2) conv_staged_kernel(const uint16_t* __restrict__ in,
+__global__ void __launch_bounds__(64 * StagedConv<CIN>::NW, 2) conv_staged_kernel(const uint16_t* __restrict__ in,
                                                              const uint16_t* __restrict__ w,
                                                              const float* __restrict__ bias, uint16_t* __restrict__ out,
                                                              float* __restrict__ out_f32, int D, int H, int W, int cout,
@@ -153,7 +155,7 @@ __global__ void __launch_bounds__(256, 2) conv_staged_kernel(const uint16_t* __r
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, c = lane & 31;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int co0 = blockIdx.y * 32;
-  const int k0 = P::KSTEPS * wave / 4, nk = P::KSTEPS * (wave + 1) / 4 - k0;
+  const int k0 = P::KSTEPS * wave / P::NW, nk = P::KSTEPS * (wave + 1) / P::NW - k0;
 
   bf16x4 wb[P::IPW];
 #pragma unroll
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__(256, 2) conv_staged_kernel(const uint16_t* __r
     const int x0 = seg * P::SEG, y0 = 2 * yp;
 
     __syncthreads();  // the previous tile's reads of LDS are done
-    for (int it = t; it < 12 * P::RV * P::SL; it += 256) {
+    for (int it = t; it < 12 * P::RV * P::SL; it += 64 * P::NW) {
       const int q = it % P::SL, v = (it / P::SL) % P::RV, row = it / (P::SL * P::RV);
       const int dz = row / 4 - 1, ys = y0 + row % 4 - 1, zs = z + dz, x = x0 + v - 1;
       uint4 val = make_uint4(0, 0, 0, 0);
@@ -210,9 +212,9 @@ __global__ void __launch_bounds__(256, 2) conv_staged_kernel(const uint16_t* __r
     __syncthreads();  // every wave is done with the staged rows; LDS now holds partial sums
 #pragma unroll
     for (int m = 0; m < P::MT; ++m) {
-      const int f = m % 4;
+      const int f = m % P::NW;
       if (wave != f) {
-        float* slot = red + (m * 3 + (wave < f ? wave : wave - 1)) * 1024;
+        float* slot = red + (m * (P::NW - 1) + (wave < f ? wave : wave - 1)) * 1024;
 #pragma unroll
         for (int r = 0; r < 16; ++r) slot[r * 64 + lane] = acc[m][r];
       }
@@ -220,15 +222,15 @@ __global__ void __launch_bounds__(256, 2) conv_staged_kernel(const uint16_t* __r
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < P::MT; ++m) {
-      const int f = m % 4;
+      const int f = m % P::NW;
       if (wave == f) {
         const int y = y0 + m / P::XT, xb = x0 + (m % P::XT) * 32;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           float sum = 0.0f;
 #pragma unroll
-          for (int ww = 0; ww < 4; ++ww)
-            sum += ww == f ? acc[m][r] : red[(m * 3 + (ww < f ? ww : ww - 1)) * 1024 + r * 64 + lane];
+          for (int ww = 0; ww < P::NW; ++ww)
+            sum += ww == f ? acc[m][r] : red[(m * (P::NW - 1) + (ww < f ? ww : ww - 1)) * 1024 + r * 64 + lane];
           const int x = xb + (r / 4) * 8 + 4 * h + (r & 3);
           if (x < W && y < H) {
             float val = sum + bb;
@@ -253,7 +255,7 @@ void launch_staged(const uint16_t* in, const uint16_t* w, const float* bias, uin
   const int ctiles = cout / 32;
   const long long want = (512 + ctiles - 1) / ctiles;  // two resident blocks on each of 256 CUs
   const unsigned gx = (unsigned)(ntiles < want ? ntiles : want);
-  hipLaunchKernelGGL(conv_staged_kernel<CIN>, dim3(gx, ctiles), dim3(256), 0, s, in, w, bias, out, out_f32, d, h, wd,
+  hipLaunchKernelGGL(conv_staged_kernel<CIN>, dim3(gx, ctiles), dim3(64 * P::NW), 0, s, in, w, bias, out, out_f32, d, h, wd,
                      cout, relu, ntiles);
 }
 
@@ -704,7 +706,7 @@ extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const floa
     case 8: launch_conv<8>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
     case 16: launch_staged<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
     case 32: launch_staged<32>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
-    case 64: launch_conv<64>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    case 64: launch_staged<64>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
     case 128: launch_conv<128>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
     default: return -1;
   }

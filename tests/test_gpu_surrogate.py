@@ -86,7 +86,7 @@ def test_conv_operators_against_reference(cin, cout):
     assert e_fwd < 1e-5 and e_wg < 1e-5 and e_bg < 1e-5
 
 
-@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 64)])
+@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 64), (64, 64)])
 def test_forward_many_tiles_against_reference(cin, cout):
     """Forward convolution where blocks walk several tiles, h is odd (the last tile's second
     row is outside the volume) and w = 70 is ragged against the tile width."""
