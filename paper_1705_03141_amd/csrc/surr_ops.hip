@@ -16,7 +16,15 @@
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][8 (l / 32) + j] and B[8 (l / 32) + j][l % 32],
+// j = 0..7, and holds D rows 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32, in accumulator r.
+__device__ __forceinline__ floatx16 mfma16(uint4 a, uint4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                 0);
+}
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -118,21 +126,22 @@ void launch_conv(const uint16_t* in, const uint16_t* w, const float* bias, uint1
 // For cin in {16, 32, 64}: a block of NW waves owns a co tile of 32 and walks tiles of two
 // output rows x SEG voxels (grid-stride).  Per tile it stages into LDS every input voxel the
 // tile reads -- 3 z-planes x 4 rows x (SEG + 2) voxels, all cin channels, zeros outside the
-// volume -- with a voxel stride of cin + 4 elements (an odd number of 8-byte pairs of banks,
-// so the 32 voxels of an A fragment fall in distinct banks).  The K dimension of the GEMM,
-// 27 cin / 8 MFMA steps of (tap, 8 input channels), is split evenly over the waves; each wave
+// volume -- with a voxel stride of cin + 8 elements (4 x an odd number of dwords, so each
+// group of 8 lanes reading 16 bytes covers all banks once).  The K dimension of the GEMM,
+// 27 cin / 16 steps of v_mfma_f32_32x32x16_bf16 over (tap, 16 input channels), is split
+// evenly over the waves; each wave
 // holds the weight fragments of its steps in registers for the whole kernel and accumulates
 // every M-tile of the output tile over them.  The NW partial sums of an M-tile are added in
 // wave order through LDS by the wave that finalizes it (m % NW).  NW = 8 for 64 channels
-// keeps a wave's weight fragments at 54 registers.
+// keeps a wave's weight fragments at 56 registers.
 template <int CIN>
 struct StagedConv {
   static constexpr int SEG = CIN == 64 ? 32 : 64;  // voxels of an output row in a tile
   static constexpr int XT = SEG / 32;              // M-tiles per output row
   static constexpr int MT = 2 * XT;                // M-tiles per tile
   static constexpr int RV = SEG + 2;               // staged voxels per row
-  static constexpr int VS = CIN + 4;               // staged voxel stride (elements)
-  static constexpr int SL = CIN / 8;               // 8-channel slices
+  static constexpr int VS = CIN + 8;               // staged voxel stride (elements)
+  static constexpr int SL = CIN / 16;              // 16-channel slices (MFMA K-steps per tap)
   static constexpr int NW = CIN == 64 ? 8 : 4;     // waves per block
   static constexpr int KSTEPS = 27 * SL;
   static constexpr int IPW = (KSTEPS + NW - 1) / NW;  // K-steps of a wave, at most
@@ -157,17 +166,17 @@ __global__ void __launch_bounds__(64 * StagedConv<CIN>::NW, 2) conv_staged_kerne
   const int co0 = blockIdx.y * 32;
   const int k0 = P::KSTEPS * wave / P::NW, nk = P::KSTEPS * (wave + 1) / P::NW - k0;
 
-  bf16x4 wb[P::IPW];
+  uint4 wb[P::IPW];
 #pragma unroll
   for (int i = 0; i < P::IPW; ++i) {
-    wb[i] = bf16x4{0, 0, 0, 0};
+    wb[i] = make_uint4(0, 0, 0, 0);
     if (i < nk) {
       const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
-      wb[i] = *reinterpret_cast<const bf16x4*>(w + ((long long)tap * cout + co0 + c) * CIN + sl * 8 + 4 * h);
+      wb[i] = *reinterpret_cast<const uint4*>(w + ((long long)tap * cout + co0 + c) * CIN + sl * 16 + 8 * h);
     }
   }
   const float bb = bias ? bias[co0 + c] : 0.0f;
-  const int lane_off = c * P::VS + 4 * h;
+  const int lane_off = c * P::VS + 8 * h;
   const int nseg = (W + P::SEG - 1) / P::SEG, nyp = (H + 1) / 2;
 
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -179,15 +188,14 @@ __global__ void __launch_bounds__(64 * StagedConv<CIN>::NW, 2) conv_staged_kerne
     const int x0 = seg * P::SEG, y0 = 2 * yp;
 
     __syncthreads();  // the previous tile's reads of LDS are done
-    for (int it = t; it < 12 * P::RV * P::SL; it += 64 * P::NW) {
-      const int q = it % P::SL, v = (it / P::SL) % P::RV, row = it / (P::SL * P::RV);
+    constexpr int Q = CIN / 8;  // 16-byte chunks of a voxel
+    for (int it = t; it < 12 * P::RV * Q; it += 64 * P::NW) {
+      const int q = it % Q, v = (it / Q) % P::RV, row = it / (Q * P::RV);
       const int dz = row / 4 - 1, ys = y0 + row % 4 - 1, zs = z + dz, x = x0 + v - 1;
       uint4 val = make_uint4(0, 0, 0, 0);
       if (zs >= 0 && zs < D && ys >= 0 && ys < H && x >= 0 && x < W)
         val = *reinterpret_cast<const uint4*>(in + (((nz + dz) * H + ys) * (long long)W + x) * CIN + 8 * q);
-      uint2* dst = reinterpret_cast<uint2*>(st + (row * P::RV + v) * P::VS + 8 * q);
-      dst[0] = make_uint2(val.x, val.y);
-      dst[1] = make_uint2(val.z, val.w);
+      *reinterpret_cast<uint4*>(st + (row * P::RV + v) * P::VS + 8 * q) = val;
     }
     __syncthreads();
 
@@ -199,12 +207,11 @@ __global__ void __launch_bounds__(64 * StagedConv<CIN>::NW, 2) conv_staged_kerne
       if (i < nk) {
         const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
         const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // each offset + 1
-        const uint16_t* a0 = st + ((dz * 4 + dy) * P::RV + dx) * P::VS + sl * 8 + lane_off;
+        const uint16_t* a0 = st + ((dz * 4 + dy) * P::RV + dx) * P::VS + sl * 16 + lane_off;
 #pragma unroll
         for (int m = 0; m < P::MT; ++m) {
           const int moff = (m / P::XT) * P::RV * P::VS + (m % P::XT) * 32 * P::VS;
-          const bf16x4 a = *reinterpret_cast<const bf16x4*>(a0 + moff);
-          acc[m] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, wb[i], acc[m], 0, 0, 0);
+          acc[m] = mfma16(*reinterpret_cast<const uint4*>(a0 + moff), wb[i], acc[m]);
         }
       }
     }
@@ -247,6 +254,202 @@ __global__ void __launch_bounds__(64 * StagedConv<CIN>::NW, 2) conv_staged_kerne
   }
 }
 
+// ---------------------------------------------------------------- forward convolution, z ring
+// For cin in {16, 32}: as the staged kernel (four waves split the K-steps, weights in
+// registers, output tiles of two rows x 64 voxels), but a block owns a column (n, row pair,
+// segment) and sweeps a range of z: the three input planes z - 1, z, z + 1 (4 rows x 66
+// voxels each) live in a ring in LDS, so each output plane stages one new plane, and the
+// loads of plane z + 2 are issued before the MFMAs of plane z and stored after them.  The
+// four partial sums of the four M-tiles are exchanged in three rounds through a separate
+// buffer: in round r wave w passes its partial of tile (w + r + 1) % 4 to the wave that owns
+// that tile, which adds it to its own (a fixed order per tile).
+template <int CIN>
+struct RingConv {
+  static constexpr int SEG = 64, XT = 2, MT = 4, NW = 4;
+  static constexpr int RV = SEG + 2;                 // staged voxels per row
+  static constexpr int VS = CIN + 8;                 // staged voxel stride (elements)
+  static constexpr int SL = CIN / 16;                // MFMA K-steps per tap
+  static constexpr int Q = CIN / 8;                  // 16-byte chunks of a voxel
+  static constexpr int KSTEPS = 27 * SL, IPW = (KSTEPS + NW - 1) / NW;
+  static constexpr int PLANE = 4 * RV * VS;          // elements of a staged plane
+  static constexpr int CHUNKS = 4 * RV * Q;          // 16-byte chunks of a plane
+  static constexpr int PF = (CHUNKS + 64 * NW - 1) / (64 * NW);  // chunks per thread
+};
+
+template <int CIN>
+__global__ void __launch_bounds__(256, 2) conv_ring_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
+                                                           const float* __restrict__ bias, uint16_t* __restrict__ out,
+                                                           float* __restrict__ out_f32, int D, int H, int W, int cout,
+                                                           int relu, int nzc, int zlen, long long nitems) {
+  using P = RingConv<CIN>;
+  __shared__ __align__(16) uint16_t ring[3 * P::PLANE];
+  __shared__ __align__(16) float xch[P::NW * 1024];
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, c = lane & 31;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int co0 = blockIdx.y * 32;
+  const int k0 = P::KSTEPS * wave / P::NW, nk = P::KSTEPS * (wave + 1) / P::NW - k0;
+
+  uint4 wb[P::IPW];
+#pragma unroll
+  for (int i = 0; i < P::IPW; ++i) {
+    wb[i] = make_uint4(0, 0, 0, 0);
+    if (i < nk) {
+      const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
+      wb[i] = *reinterpret_cast<const uint4*>(w + ((long long)tap * cout + co0 + c) * CIN + sl * 16 + 8 * h);
+    }
+  }
+  const float bb = bias ? bias[co0 + c] : 0.0f;
+  const int lane_off = c * P::VS + 8 * h;
+  const int nseg = (W + P::SEG - 1) / P::SEG, nyp = (H + 1) / 2;
+  const long long plane_elems = (long long)H * W * CIN;
+  // wave w owns output tile w: row y0 + w / 2, voxels x0 + 32 (w % 2) ..
+  const int my_row = wave / P::XT, my_x = (wave % P::XT) * 32;
+
+  // the staged chunks this thread moves: offset within an input plane (-1 where the voxel
+  // is outside the plane or the chunk index is past the plane)
+  int src_off[P::PF];
+
+  auto store_plane = [&](int p, const uint4(&buf)[P::PF]) {
+    uint16_t* dst = ring + ((p + 3) % 3) * P::PLANE;
+#pragma unroll
+    for (int k = 0; k < P::PF; ++k) {
+      const int it = t + 64 * P::NW * k;
+      if (it < P::CHUNKS) {
+        const int q = it % P::Q, v = (it / P::Q) % P::RV, r = it / (P::Q * P::RV);
+        *reinterpret_cast<uint4*>(dst + (r * P::RV + v) * P::VS + 8 * q) = buf[k];
+      }
+    }
+  };
+
+#pragma unroll 1
+  for (long long item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int zc = (int)(item % nzc);
+    const long long col = item / nzc;  // (n nyp + yp) nseg + seg
+    const int seg = (int)(col % nseg);
+    const int yp = (int)((col / nseg) % nyp);
+    const long long nb = col / ((long long)nseg * nyp);
+    const int x0 = seg * P::SEG, y0 = 2 * yp;
+    const int za = zc * zlen, zb = min(D, za + zlen);
+    const uint16_t* in_n = in + nb * D * plane_elems;
+#pragma unroll
+    for (int k = 0; k < P::PF; ++k) {
+      const int it = t + 64 * P::NW * k;
+      src_off[k] = -1;
+      if (it < P::CHUNKS) {
+        const int q = it % P::Q, v = (it / P::Q) % P::RV, r = it / (P::Q * P::RV);
+        const int ys = y0 + r - 1, x = x0 + v - 1;
+        if (ys >= 0 && ys < H && x >= 0 && x < W) src_off[k] = (ys * W + x) * CIN + 8 * q;
+      }
+    }
+    auto load = [&](int p, uint4(&buf)[P::PF]) {
+      const bool pin = p >= 0 && p < D;
+      const uint16_t* base = in_n + (long long)p * plane_elems;
+#pragma unroll
+      for (int k = 0; k < P::PF; ++k) {
+        buf[k] = make_uint4(0, 0, 0, 0);
+        if (pin && src_off[k] >= 0) buf[k] = *reinterpret_cast<const uint4*>(base + src_off[k]);
+      }
+    };
+
+    uint4 pf[P::PF];
+    __syncthreads();  // the previous item's reads of the ring are done
+    load(za - 1, pf);
+    store_plane(za - 1, pf);
+    load(za, pf);
+    store_plane(za, pf);
+    load(za + 1, pf);
+    int sm = ((za + 2) % 3) * P::PLANE, s0 = (za % 3) * P::PLANE, sp = ((za + 1) % 3) * P::PLANE;  // z - 1, z, z + 1
+#pragma unroll 1
+    for (int z = za; z < zb; ++z) {
+      store_plane(z + 1, pf);  // its slot held plane z - 2, last read before the previous exchange
+      __syncthreads();
+      if (z + 1 < zb) load(z + 2, pf);
+
+      floatx16 acc[P::MT];
+#pragma unroll
+      for (int m = 0; m < P::MT; ++m) acc[m] = floatx16{};
+      int lo = lane_off;
+      asm volatile("" : "+v"(lo));  // keeps the per-step A addresses inside the z loop
+#pragma unroll
+      for (int i = 0; i < P::IPW; ++i) {
+        if (i < nk) {
+          const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
+          const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // each offset + 1
+          const int sb = dz == 0 ? sm : (dz == 1 ? s0 : sp);
+          const uint16_t* a0 = ring + sb + (dy * P::RV + dx) * P::VS + sl * 16 + lo;
+#pragma unroll
+          for (int m = 0; m < P::MT; ++m) {
+            const int moff = (m / P::XT) * P::RV * P::VS + (m % P::XT) * 32 * P::VS;
+            acc[m] = mfma16(*reinterpret_cast<const uint4*>(a0 + moff), wb[i], acc[m]);
+          }
+        }
+      }
+      {
+        const int tmp = sm;
+        sm = s0;
+        s0 = sp;
+        sp = tmp;
+      }
+
+      // the partial sums: round r, wave w sends tile (w + r + 1) % 4 and adds the one from
+      // wave (w - r - 1) % 4 to its own tile w (copies chosen by wave-uniform branches keep
+      // the accumulators in registers)
+      floatx16 mine = acc[0];
+      if (wave == 1) mine = acc[1];
+      if (wave == 2) mine = acc[2];
+      if (wave == 3) mine = acc[3];
+#pragma unroll
+      for (int r = 0; r < P::NW - 1; ++r) {
+        const int send = (wave + r + 1) % P::NW, from = (wave + P::NW - r - 1) % P::NW;
+        floatx16 snd = acc[0];
+        if (send == 1) snd = acc[1];
+        if (send == 2) snd = acc[2];
+        if (send == 3) snd = acc[3];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) xch[wave * 1024 + e * 64 + lane] = snd[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) mine[e] += xch[from * 1024 + e * 64 + lane];
+        __syncthreads();
+      }
+      const int y = y0 + my_row;
+      if (y < H) {
+        const long long vrow = ((nb * D + z) * H + y) * (long long)W;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int x = x0 + my_x + (e / 4) * 8 + 4 * h + (e & 3);
+          if (x < W) {
+            float val = mine[e] + bb;
+            if (relu) val = fmaxf(val, 0.0f);
+            const long long o = (vrow + x) * cout + co0 + c;
+            if (out_f32)
+              out_f32[o] = val;
+            else
+              out[o] = f2bf(val);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int CIN>
+void launch_ring(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, float* out_f32, int n, int d,
+                 int h, int wd, int cout, int relu, hipStream_t s) {
+  using P = RingConv<CIN>;
+  const int ctiles = cout / 32;
+  const long long ncols = (long long)n * ((h + 1) / 2) * ((wd + P::SEG - 1) / P::SEG);
+  const long long target = (512 + ctiles - 1) / ctiles;  // two resident blocks on each of 256 CUs
+  long long nzc = (target + ncols - 1) / ncols;
+  if (nzc > d) nzc = d;
+  const int zlen = (int)((d + nzc - 1) / nzc);
+  nzc = (d + zlen - 1) / zlen;
+  const long long nitems = ncols * nzc;
+  const unsigned gx = (unsigned)(nitems < target ? nitems : target);
+  hipLaunchKernelGGL(conv_ring_kernel<CIN>, dim3(gx, ctiles), dim3(256), 0, s, in, w, bias, out, out_f32, d, h, wd, cout,
+                     relu, (int)nzc, zlen, nitems);
+}
+
 template <int CIN>
 void launch_staged(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, float* out_f32, int n,
                    int d, int h, int wd, int cout, int relu, hipStream_t s) {
@@ -278,14 +481,14 @@ __global__ void flip_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict
 // the nine taps with dz = k - 1.  Per segment the block stages dout^T [co][x] into LDS, and
 // wave k stages the source rows (z + dz, y') as in^T [ci][x] over x0 - 4 .. x0 + kSeg + 3;
 // the three rows y - 1, y, y + 1 live in a ring, so the next segment of the same column
-// stages only row y + 2.  The K order of an MFMA is free: lane half h takes voxels
-// x0 + 32 h + 4 s + j at step s, so each lane walks its 32 voxels four at a time and the
-// dx = -1, +1 operands are its aligned 8-byte words shifted by one element, the word
-// before or after coming from the previous or the next step.
+// stages only row y + 2.  The K order of an MFMA is free: with v_mfma_f32_32x32x16_bf16 lane
+// half h takes voxels x0 + 32 h + 8 s + j at step s, so each lane walks its 32 voxels eight
+// at a time and the dx = -1, +1 operands are its aligned 16-byte words shifted by one
+// element, the word before or after coming from the previous or the next step.
 constexpr int kSeg = 64;            // voxels per row segment
-constexpr int kRsA = kSeg + 4;      // LDS row stride of dout^T (elements; 34 dwords)
-constexpr int kRowB = kSeg + 8;     // staged source row, x0 - 4 .. x0 + kSeg + 3
-constexpr int kRsB = kRowB + 4;     // LDS row stride of in^T (38 dwords)
+constexpr int kRsA = kSeg + 8;      // LDS row stride of dout^T (elements; 36 dwords)
+constexpr int kRowB = kSeg + 16;    // staged source row, x0 - 8 .. x0 + kSeg + 7
+constexpr int kRsB = kRowB + 8;     // LDS row stride of in^T (44 dwords)
 constexpr int kWgradBlocks = 768;   // three resident blocks on each of 256 compute units
 
 __host__ __device__ inline int nseg_of(int W) { return (W + kSeg - 1) / kSeg; }
@@ -306,7 +509,16 @@ inline WgradPlan wgrad_plan(int n, int d, int h, int wd, int cin, int cout) {
   return p;
 }
 
-__device__ __forceinline__ bf16x4 as_bf16x4(uint64_t u) { return __builtin_bit_cast(bf16x4, u); }
+// [p.e7, c.e0 .. c.e6] and [c.e1 .. c.e7, n.e0] of 8-element BF16 words (element 2i in the
+// low half of dword i)
+__device__ __forceinline__ uint4 shift_in_prev(uint4 p, uint4 c) {
+  return make_uint4((c.x << 16) | (p.w >> 16), (c.y << 16) | (c.x >> 16), (c.z << 16) | (c.y >> 16),
+                    (c.w << 16) | (c.z >> 16));
+}
+__device__ __forceinline__ uint4 shift_in_next(uint4 c, uint4 n) {
+  return make_uint4((c.x >> 16) | (c.y << 16), (c.y >> 16) | (c.z << 16), (c.z >> 16) | (c.w << 16),
+                    (c.w >> 16) | (n.x << 16));
+}
 
 __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ dout,
                                                        float* __restrict__ part, float* __restrict__ bpart, int D, int H,
@@ -369,7 +581,7 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
       const long long base = ((nz + dz) * H + yy) * (long long)W;
       uint16_t* dst = sB[wave][(yy + 3) % 3];
       for (int it = lane; it < 4 * kRowB; it += 64) {
-        const int q = it & 3, xi = it >> 2, x = x0 - 4 + xi;
+        const int q = it & 3, xi = it >> 2, x = x0 - 8 + xi;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (row_ok && x >= 0 && x < W && ci0 + 8 * q < cin)
           v = *reinterpret_cast<const uint4*>(in + (base + x) * cin + ci0 + 8 * q);
@@ -383,24 +595,22 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
     const int h = lane >> 5, c = lane & 31;
     const uint16_t* pa = sA + c * kRsA + 32 * h;
     const uint16_t* pb[3];
-    uint64_t prv[3], cur[3];
+    uint4 prv[3], cur[3];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
-      pb[dy] = sB[wave][(y + dy + 2) % 3] + c * kRsB + 32 * h;
-      prv[dy] = *reinterpret_cast<const uint64_t*>(pb[dy]);
-      cur[dy] = *reinterpret_cast<const uint64_t*>(pb[dy] + 4);
+      pb[dy] = sB[wave][(y + dy + 2) % 3] + c * kRsB + 32 * h;  // element 8 + 32 h is voxel x0 + 32 h
+      prv[dy] = *reinterpret_cast<const uint4*>(pb[dy]);
+      cur[dy] = *reinterpret_cast<const uint4*>(pb[dy] + 8);
     }
 #pragma unroll
-    for (int st = 0; st < kSeg / 8; ++st) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(pa + 4 * st);
+    for (int st = 0; st < kSeg / 16; ++st) {
+      const uint4 a = *reinterpret_cast<const uint4*>(pa + 8 * st);
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
-        const uint64_t nxt = *reinterpret_cast<const uint64_t*>(pb[dy] + 8 + 4 * st);
-        const uint64_t bm = (cur[dy] << 16) | (prv[dy] >> 48);  // voxels x - 1 .. x + 2
-        const uint64_t bp = (cur[dy] >> 16) | (nxt << 48);      // voxels x + 1 .. x + 4
-        acc[3 * dy + 0] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, as_bf16x4(bm), acc[3 * dy + 0], 0, 0, 0);
-        acc[3 * dy + 1] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, as_bf16x4(cur[dy]), acc[3 * dy + 1], 0, 0, 0);
-        acc[3 * dy + 2] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, as_bf16x4(bp), acc[3 * dy + 2], 0, 0, 0);
+        const uint4 nxt = *reinterpret_cast<const uint4*>(pb[dy] + 16 + 8 * st);
+        acc[3 * dy + 0] = mfma16(a, shift_in_prev(prv[dy], cur[dy]), acc[3 * dy + 0]);  // voxels x - 1 ..
+        acc[3 * dy + 1] = mfma16(a, cur[dy], acc[3 * dy + 1]);
+        acc[3 * dy + 2] = mfma16(a, shift_in_next(cur[dy], nxt), acc[3 * dy + 2]);      // voxels x + 1 ..
         prv[dy] = cur[dy];
         cur[dy] = nxt;
       }
@@ -704,8 +914,18 @@ extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const floa
   const long long nvox = (long long)n * d * h * wd;
   switch (cin) {
     case 8: launch_conv<8>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
-    case 16: launch_staged<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
-    case 32: launch_staged<32>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
+    case 16:
+      if ((long long)h * wd * 16 < (1LL << 31))
+        launch_ring<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
+      else
+        launch_staged<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
+      break;
+    case 32:
+      if ((long long)h * wd * 32 < (1LL << 31))
+        launch_ring<32>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
+      else
+        launch_staged<32>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
+      break;
     case 64: launch_staged<64>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream)); break;
     case 128: launch_conv<128>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
     default: return -1;

@@ -86,13 +86,14 @@ def test_conv_operators_against_reference(cin, cout):
     assert e_fwd < 1e-5 and e_wg < 1e-5 and e_bg < 1e-5
 
 
-@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 64), (64, 64)])
-def test_forward_many_tiles_against_reference(cin, cout):
-    """Forward convolution where blocks walk several tiles, h is odd (the last tile's second
-    row is outside the volume) and w = 70 is ragged against the tile width."""
+@pytest.mark.parametrize("cin,cout,d", [(16, 32, 48), (32, 64, 48), (64, 64, 8)])
+def test_forward_many_tiles_against_reference(cin, cout, d):
+    """Forward convolution where blocks walk several tiles (16 and 32 channels: ranges of 4
+    z-planes through the ring of input planes), h is odd (the last tile's second row is
+    outside the volume) and w = 70 is ragged against the tile width."""
     import torch
     rng = np.random.default_rng(cin * cout)
-    n, d, h, w = 1, 8, 41, 70
+    n, h, w = 1, 41, 70
     x = bf16_round(rng.normal(size=(n, d, h, w, cin)))
     wt = bf16_round(rng.normal(size=(27, cout, cin)) * 0.1)
     b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
@@ -108,6 +109,37 @@ def test_forward_many_tiles_against_reference(cin, cout):
     e_relu = rel(from_dev_bf16(yb), bf16_round(np.maximum(ref, 0.0)))
     log(f"[conv {n}x{d}x{h}x{w} {cin}->{cout}] fwd {e_fwd:.2e} relu/bf16 {e_relu:.2e}")
     assert e_fwd < 1e-5 and e_relu < 1e-2
+
+
+def test_forward_full_size_sampled():
+    """The 32 -> 32 convolution at the surrogate's full resolution (1 x 256 x 64 x 64; each
+    block sweeps 16 z-planes) on 300 sampled output voxels, each summed over its 27 taps
+    directly in FP64 from the same BF16 operands."""
+    import torch
+    rng = np.random.default_rng(3)
+    n, d, h, w, cin, cout = 1, 256, 64, 64, 32, 32
+    L = S._lib()
+    x = bf16_round(rng.normal(size=(n, d, h, w, cin)).astype(np.float32))
+    wt = bf16_round(rng.normal(size=(27, cout, cin)) * 0.1)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    xd, wd = to_dev_bf16(x), to_dev_bf16(wt)
+    bd = torch.from_numpy(b.astype(np.float32)).to("cuda")
+    y32 = torch.empty((n, d, h, w, cout), dtype=torch.float32, device="cuda")
+    assert L.surr_conv3d_fwd(S._p(xd), S._p(wd), S._p(bd), None, S._p(y32), n, d, h, w, cin, cout, 0, None) == 0
+    y = y32.cpu().numpy()
+    idx = np.stack([rng.integers(0, s, 300) for s in (d, h, w)], axis=1)
+    idx[:4] = [[0, 0, 0], [d - 1, h - 1, w - 1], [15, 63, 0], [16, 0, 63]]  # faces and z-range ends
+    worst = 0.0
+    for z, yy, xx in idx:
+        ref = b.copy()
+        for tap in range(27):
+            dz, dy, dx = tap // 9 - 1, (tap // 3) % 3 - 1, tap % 3 - 1
+            zs, ys, xs = z + dz, yy + dy, xx + dx
+            if 0 <= zs < d and 0 <= ys < h and 0 <= xs < w:
+                ref += wt[tap] @ x[0, zs, ys, xs]
+        worst = max(worst, float(np.abs(y[0, z, yy, xx] - ref).max() / max(np.abs(ref).max(), 1e-30)))
+    log(f"[conv full size 1x256x64x64 32->32] sampled worst relative error {worst:.2e}")
+    assert worst < 1e-5
 
 
 def test_weight_gradient_long_ranges_against_reference():
