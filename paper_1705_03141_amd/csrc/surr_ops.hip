@@ -33,6 +33,22 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
+__device__ __forceinline__ void unpack8(uint4 u, float (&f)[8]) {
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f[2 * i] = __uint_as_float(w[i] << 16);
+    f[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+  }
+}
+
+__device__ __forceinline__ uint4 pack8(const float (&f)[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 constexpr int kTapOff[27][3] = {
     {-1, -1, -1}, {-1, -1, 0}, {-1, -1, 1}, {-1, 0, -1}, {-1, 0, 0}, {-1, 0, 1}, {-1, 1, -1}, {-1, 1, 0}, {-1, 1, 1},
     {0, -1, -1},  {0, -1, 0},  {0, -1, 1},  {0, 0, -1},  {0, 0, 0},  {0, 0, 1},  {0, 1, -1},  {0, 1, 0},  {0, 1, 1},
@@ -489,6 +505,13 @@ constexpr int kSeg = 64;            // voxels per row segment
 constexpr int kRsA = kSeg + 8;      // LDS row stride of dout^T (elements; 36 dwords)
 constexpr int kRowB = kSeg + 16;    // staged source row, x0 - 8 .. x0 + kSeg + 7
 constexpr int kRsB = kRowB + 8;     // LDS row stride of in^T (44 dwords)
+// Channel row r of a staged tile starts at r * stride + (r / 8) * 16 elements: the 8-dword
+// shift per group of 8 rows spreads the transposing 2-byte stores of the four 8-channel
+// groups over distinct banks (stride * 8 is a multiple of 32 dwords); 16-byte reads along x
+// keep their conflict-free pattern.
+__host__ __device__ constexpr int trow(int r, int stride) { return r * stride + (r >> 3) * 16; }
+constexpr int kTileA = 32 * kRsA + 4 * 16;  // elements of a staged dout^T tile
+constexpr int kTileB = 32 * kRsB + 4 * 16;  // elements of a staged in^T row
 constexpr int kWgradBlocks = 768;   // three resident blocks on each of 256 compute units
 
 __host__ __device__ inline int nseg_of(int W) { return (W + kSeg - 1) / kSeg; }
@@ -524,8 +547,8 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
                                                        float* __restrict__ part, float* __restrict__ bpart, int D, int H,
                                                        int W, int cin, int cout, long long nsr, int nchunks,
                                                        int ci_tiles) {
-  __shared__ __align__(16) uint16_t sA[32 * kRsA];
-  __shared__ __align__(16) uint16_t sB[3][3][32 * kRsB];
+  __shared__ __align__(16) uint16_t sA[kTileA];
+  __shared__ __align__(16) uint16_t sB[3][3][kTileB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, dz = wave - 1;
   const int chunk = blockIdx.x;
   const int co0 = (blockIdx.y / ci_tiles) * 32, ci0 = (blockIdx.y % ci_tiles) * 32;
@@ -536,12 +559,65 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
   floatx16 acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = floatx16{};
-  float bsum[2][8];
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) bsum[k][i] = 0.0f;
+  float bsum = 0.0f;  // wave 0, lane (h, c): channel co0 + c over voxels x0 + 32 h .. + 31
 
+  // 16-byte chunks this thread moves: dout^T item t + 192 k -> (voxel x0 + it / 4, channels
+  // co0 + 8 (it % 4) ..); in^T item lane + 64 k -> (voxel x0 - 8 + it / 4, channels ci0 + 8 (it % 4) ..)
+  constexpr int PB = (4 * kRowB + 63) / 64;
+  auto load_dout = [&](long long nz, int y, int x0, uint4 (&buf)[2]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = t + 192 * k;
+      buf[k] = make_uint4(0, 0, 0, 0);
+      const int x = x0 + (it >> 2);
+      if (it < 256 && x < W)
+        buf[k] = *reinterpret_cast<const uint4*>(dout + ((nz * H + y) * (long long)W + x) * cout + co0 + 8 * (it & 3));
+    }
+  };
+  auto store_dout = [&](const uint4 (&buf)[2]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = t + 192 * k;
+      if (it < 256) {
+        const int q = it & 3, xi = it >> 2;
+        const uint32_t wv[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sA[trow(8 * q + i, kRsA) + xi] = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
+      }
+    }
+  };
+  auto load_row = [&](long long nz, int z, int yy, int x0, uint4 (&buf)[PB]) {
+    const int zz = z + dz;
+    const bool row_ok = zz >= 0 && zz < D && yy >= 0 && yy < H;
+    const long long base = ((nz + dz) * H + yy) * (long long)W;
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      const int it = lane + 64 * k;
+      const int q = it & 3, x = x0 - 8 + (it >> 2);
+      buf[k] = make_uint4(0, 0, 0, 0);
+      if (it < 4 * kRowB && row_ok && x >= 0 && x < W && ci0 + 8 * q < cin)
+        buf[k] = *reinterpret_cast<const uint4*>(in + (base + x) * cin + ci0 + 8 * q);
+    }
+  };
+  auto store_row = [&](int yy, const uint4 (&buf)[PB]) {
+    uint16_t* dst = sB[wave][(yy + 3) % 3];
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      const int it = lane + 64 * k;
+      if (it < 4 * kRowB) {
+        const int q = it & 3, xi = it >> 2;
+        const uint32_t wv[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[trow(8 * q + i, kRsB) + xi] = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
+      }
+    }
+  };
+
+  // a segment continues the previous one's column when it is the next y of the same
+  // (n, z, segment); its dout row and its one new source row are then loaded during the
+  // previous segment's MFMAs
+  uint4 pfa[2], pfb[PB];
+  bool have = false;
   long long prev_col = -1;
   int prev_y = -2;
   for (long long r = r0; r < r1; ++r) {
@@ -556,49 +632,42 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
     prev_y = y;
     __syncthreads();  // the previous segment's reads of LDS are done
 
-    // dout^T of row (nz, y): item it -> voxel x0 + it / 4, channels co0 + 8 (it % 4) + 0..7
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int it = t + 192 * k;
-      if (it < 256) {
-        const int q = it & 3, xi = it >> 2, x = x0 + xi;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (x < W) v = *reinterpret_cast<const uint4*>(dout + ((nz * H + y) * (long long)W + x) * cout + co0 + 8 * q);
-        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint16_t e = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
-          sA[(8 * q + i) * kRsA + xi] = e;
-          if (do_bias) bsum[k][i] += bf2f(e);
-        }
+    if (have) {
+      store_dout(pfa);
+      store_row(y + 1, pfb);
+    } else {
+      uint4 tb[2];
+      load_dout(nz, y, x0, tb);
+      store_dout(tb);
+      for (int yy = cont ? y + 1 : y - 1; yy <= y + 1; ++yy) {
+        uint4 rb[PB];
+        load_row(nz, z, yy, x0, rb);
+        store_row(yy, rb);
       }
     }
-    // in^T of the source rows (z + dz, yy) this wave needs: yy = y + 1 when the segment
-    // continues the previous one's column, else y - 1, y, y + 1
-    const int zz = z + dz;
-    for (int yy = cont ? y + 1 : y - 1; yy <= y + 1; ++yy) {
-      const bool row_ok = zz >= 0 && zz < D && yy >= 0 && yy < H;
-      const long long base = ((nz + dz) * H + yy) * (long long)W;
-      uint16_t* dst = sB[wave][(yy + 3) % 3];
-      for (int it = lane; it < 4 * kRowB; it += 64) {
-        const int q = it & 3, xi = it >> 2, x = x0 - 8 + xi;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (row_ok && x >= 0 && x < W && ci0 + 8 * q < cin)
-          v = *reinterpret_cast<const uint4*>(in + (base + x) * cin + ci0 + 8 * q);
-        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) dst[(8 * q + i) * kRsB + xi] = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
-      }
+    have = r + 1 < r1 && y + 1 < H;  // the next segment continues this column
+    if (have) {
+      load_dout(nz, y + 1, x0, pfa);
+      load_row(nz, z, y + 2, x0, pfb);
     }
     __syncthreads();
 
     const int h = lane >> 5, c = lane & 31;
-    const uint16_t* pa = sA + c * kRsA + 32 * h;
+    const uint16_t* pa = sA + trow(c, kRsA) + 32 * h;
+    if (do_bias && wave == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float f[8];
+        unpack8(*reinterpret_cast<const uint4*>(pa + 8 * j), f);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bsum += f[i];
+      }
+    }
     const uint16_t* pb[3];
     uint4 prv[3], cur[3];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
-      pb[dy] = sB[wave][(y + dy + 2) % 3] + c * kRsB + 32 * h;  // element 8 + 32 h is voxel x0 + 32 h
+      pb[dy] = sB[wave][(y + dy + 2) % 3] + trow(c, kRsB) + 32 * h;  // element 8 + 32 h is voxel x0 + 32 h
       prv[dy] = *reinterpret_cast<const uint4*>(pb[dy]);
       cur[dy] = *reinterpret_cast<const uint4*>(pb[dy] + 8);
     }
@@ -633,21 +702,10 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
   }
   if (do_bias) {
     __syncthreads();
-    float* red = reinterpret_cast<float*>(&sB[0][0][0]);  // [256 items][8]
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int it = t + 192 * k;
-      if (it < 256)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) red[it * 8 + i] = bsum[k][i];
-    }
+    float* red = reinterpret_cast<float*>(&sB[0][0][0]);
+    if (t < 64) red[t] = bsum;
     __syncthreads();
-    if (t < 32) {
-      const int q = t >> 3, i = t & 7;
-      float sum = 0.0f;
-      for (int xi = 0; xi < kSeg; ++xi) sum += red[(xi * 4 + q) * 8 + i];
-      bpart[(long long)chunk * cout + co0 + t] = sum;
-    }
+    if (t < 32) bpart[(long long)chunk * cout + co0 + t] = red[t] + red[t + 32];
   }
 }
 
@@ -683,22 +741,6 @@ inline void launch_chunk_sum(const float* part, float* out, long long len, int n
 // The element-wise operators move 8 channels (16 bytes) per thread; channel counts are
 // multiples of 8 wherever they are called with voxel layouts, and the flat operators take a
 // scalar tail.
-__device__ __forceinline__ void unpack8(uint4 u, float (&f)[8]) {
-  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    f[2 * i] = __uint_as_float(w[i] << 16);
-    f[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
-  }
-}
-
-__device__ __forceinline__ uint4 pack8(const float (&f)[8]) {
-  uint32_t w[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
-  return make_uint4(w[0], w[1], w[2], w[3]);
-}
-
 __global__ void relu_bwd_kernel(const uint16_t* __restrict__ y, const uint16_t* __restrict__ dy,
                                 uint16_t* __restrict__ dx, long long count, int vec) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
