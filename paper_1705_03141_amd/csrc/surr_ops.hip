@@ -271,22 +271,24 @@ __global__ void __launch_bounds__(64 * StagedConv<CIN>::NW, 2) conv_staged_kerne
 }
 
 // ---------------------------------------------------------------- forward convolution, z ring
-// For cin in {16, 32}: as the staged kernel (four waves split the K-steps, weights in
+// For cin in {8, 16, 32}: as the staged kernel (four waves split the K-steps, weights in
 // registers, output tiles of two rows x 64 voxels), but a block owns a column (n, row pair,
 // segment) and sweeps a range of z: the three input planes z - 1, z, z + 1 (4 rows x 66
 // voxels each) live in a ring in LDS, so each output plane stages one new plane, and the
 // loads of plane z + 2 are issued before the MFMAs of plane z and stored after them.  The
 // four partial sums of the four M-tiles are exchanged in three rounds through a separate
 // buffer: in round r wave w passes its partial of tile (w + r + 1) % 4 to the wave that owns
-// that tile, which adds it to its own (a fixed order per tile).
+// that tile, which adds it to its own (a fixed order per tile).  With 8 channels a K-step
+// pairs two taps: lane half h takes tap 2 k + h (k = 13: tap 26 and a zero weight), and the
+// voxel stride of 8 elements (4 dwords) is already conflict-free.
 template <int CIN>
 struct RingConv {
   static constexpr int SEG = 64, XT = 2, MT = 4, NW = 4;
   static constexpr int RV = SEG + 2;                 // staged voxels per row
-  static constexpr int VS = CIN + 8;                 // staged voxel stride (elements)
-  static constexpr int SL = CIN / 16;                // MFMA K-steps per tap
+  static constexpr int VS = CIN == 8 ? 8 : CIN + 8;  // staged voxel stride (elements)
+  static constexpr int SL = CIN == 8 ? 1 : CIN / 16; // MFMA K-steps per tap (per tap pair for 8)
   static constexpr int Q = CIN / 8;                  // 16-byte chunks of a voxel
-  static constexpr int KSTEPS = 27 * SL, IPW = (KSTEPS + NW - 1) / NW;
+  static constexpr int KSTEPS = CIN == 8 ? 14 : 27 * SL, IPW = (KSTEPS + NW - 1) / NW;
   static constexpr int PLANE = 4 * RV * VS;          // elements of a staged plane
   static constexpr int CHUNKS = 4 * RV * Q;          // 16-byte chunks of a plane
   static constexpr int PF = (CHUNKS + 64 * NW - 1) / (64 * NW);  // chunks per thread
@@ -310,12 +312,18 @@ __global__ void __launch_bounds__(256, 2) conv_ring_kernel(const uint16_t* __res
   for (int i = 0; i < P::IPW; ++i) {
     wb[i] = make_uint4(0, 0, 0, 0);
     if (i < nk) {
-      const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
-      wb[i] = *reinterpret_cast<const uint4*>(w + ((long long)tap * cout + co0 + c) * CIN + sl * 16 + 8 * h);
+      const int k = k0 + i;
+      if constexpr (CIN == 8) {
+        const int tap = 2 * k + h;
+        if (tap < 27) wb[i] = *reinterpret_cast<const uint4*>(w + ((long long)tap * cout + co0 + c) * CIN);
+      } else {
+        const int tap = k / P::SL, sl = k % P::SL;
+        wb[i] = *reinterpret_cast<const uint4*>(w + ((long long)tap * cout + co0 + c) * CIN + sl * 16 + 8 * h);
+      }
     }
   }
   const float bb = bias ? bias[co0 + c] : 0.0f;
-  const int lane_off = c * P::VS + 8 * h;
+  const int lane_off = c * P::VS + (CIN == 8 ? 0 : 8 * h);
   const int nseg = (W + P::SEG - 1) / P::SEG, nyp = (H + 1) / 2;
   const long long plane_elems = (long long)H * W * CIN;
   // wave w owns output tile w: row y0 + w / 2, voxels x0 + 32 (w % 2) ..
@@ -389,7 +397,15 @@ __global__ void __launch_bounds__(256, 2) conv_ring_kernel(const uint16_t* __res
 #pragma unroll
       for (int i = 0; i < P::IPW; ++i) {
         if (i < nk) {
-          const int k = k0 + i, tap = k / P::SL, sl = k % P::SL;
+          const int k = k0 + i;
+          int tap, sl;
+          if constexpr (CIN == 8) {
+            tap = min(2 * k + h, 26);  // lane-dependent; the zero weight of tap 27 reads tap 26
+            sl = 0;
+          } else {
+            tap = k / P::SL;
+            sl = k % P::SL;
+          }
           const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // each offset + 1
           const int sb = dz == 0 ? sm : (dz == 1 ? s0 : sp);
           const uint16_t* a0 = ring + sb + (dy * P::RV + dx) * P::VS + sl * 16 + lo;
@@ -512,7 +528,7 @@ constexpr int kRsB = kRowB + 8;     // LDS row stride of in^T (44 dwords)
 __host__ __device__ constexpr int trow(int r, int stride) { return r * stride + (r >> 3) * 16; }
 constexpr int kTileA = 32 * kRsA + 4 * 16;  // elements of a staged dout^T tile
 constexpr int kTileB = 32 * kRsB + 4 * 16;  // elements of a staged in^T row
-constexpr int kWgradBlocks = 768;   // three resident blocks on each of 256 compute units
+constexpr int kWgradBlocks = 512;   // two resident blocks (LDS-bound) on each of 256 compute units
 
 __host__ __device__ inline int nseg_of(int W) { return (W + kSeg - 1) / kSeg; }
 
@@ -712,11 +728,19 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
 // out[i] = sum over k of part[k][i], i < len.  A block of 256 threads covers OPB outputs with
 // G = 256 / OPB groups; group g adds chunks g, g + G, ... in order, and the G group sums are
 // added in group order, so the result does not depend on scheduling.
-__global__ void __launch_bounds__(256) chunk_sum_kernel(const float* __restrict__ part, float* __restrict__ out,
-                                                        long long len, int nchunks, int opb) {
+// Two sums share the launch: blocks [0, nb1) cover (part1, out1, len1), the rest (part2,
+// out2, len2).
+__global__ void __launch_bounds__(256) chunk_sum_kernel(const float* __restrict__ part1, float* __restrict__ out1,
+                                                        long long len1, const float* __restrict__ part2,
+                                                        float* __restrict__ out2, long long len2, long long nb1,
+                                                        int nchunks, int opb) {
   __shared__ float sred[256];
+  const bool first = blockIdx.x < nb1;
+  const float* __restrict__ part = first ? part1 : part2;
+  float* __restrict__ out = first ? out1 : out2;
+  const long long len = first ? len1 : len2;
   const int t = threadIdx.x, o = t % opb, g = t / opb, G = 256 / opb;
-  const long long i = (long long)blockIdx.x * opb + o;
+  const long long i = (first ? (long long)blockIdx.x : (long long)blockIdx.x - nb1) * opb + o;
   float s = 0.0f;
   if (i < len) {
 #pragma unroll 4
@@ -731,10 +755,13 @@ __global__ void __launch_bounds__(256) chunk_sum_kernel(const float* __restrict_
   }
 }
 
-inline void launch_chunk_sum(const float* part, float* out, long long len, int nchunks, hipStream_t s) {
-  const int opb = len >= 64 ? 64 : 32;
-  hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)((len + opb - 1) / opb)), dim3(256), 0, s, part, out, len,
-                     nchunks, opb);
+// out1 = chunk sums of part1 (len1 >= 32), and of part2 into out2 when out2 is not null
+inline void launch_chunk_sums(const float* part1, float* out1, long long len1, const float* part2, float* out2,
+                              long long len2, int nchunks, hipStream_t s) {
+  const int opb = 32;
+  const long long nb1 = (len1 + opb - 1) / opb, nb2 = out2 ? (len2 + opb - 1) / opb : 0;
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)(nb1 + nb2)), dim3(256), 0, s, part1, out1, len1, part2, out2,
+                     len2, nb1, nchunks, opb);
 }
 
 // ---------------------------------------------------------------- element-wise operators
@@ -955,7 +982,12 @@ extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const floa
     return -1;
   const long long nvox = (long long)n * d * h * wd;
   switch (cin) {
-    case 8: launch_conv<8>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream)); break;
+    case 8:
+      if ((long long)h * wd * 8 < (1LL << 31))
+        launch_ring<8>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
+      else
+        launch_conv<8>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream));
+      break;
     case 16:
       if ((long long)h * wd * 16 < (1LL << 31))
         launch_ring<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
@@ -1005,8 +1037,7 @@ extern "C" int surr_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float
   float* bpart = part + (size_t)p.nchunks * 27 * cout * cin;
   hipLaunchKernelGGL(wgrad_kernel, dim3(p.nchunks, p.tiles), dim3(192), 0, S(stream), in, dout, part,
                      dbias ? bpart : nullptr, d, h, wd, cin, cout, p.nsr, p.nchunks, p.ci_tiles);
-  launch_chunk_sum(part, dw, 27LL * cout * cin, p.nchunks, S(stream));
-  if (dbias) launch_chunk_sum(bpart, dbias, (long long)cout, p.nchunks, S(stream));
+  launch_chunk_sums(part, dw, 27LL * cout * cin, bpart, dbias, (long long)cout, p.nchunks, S(stream));
   return done();
 }
 

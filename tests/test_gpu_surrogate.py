@@ -86,7 +86,7 @@ def test_conv_operators_against_reference(cin, cout):
     assert e_fwd < 1e-5 and e_wg < 1e-5 and e_bg < 1e-5
 
 
-@pytest.mark.parametrize("cin,cout,d", [(16, 32, 48), (32, 64, 48), (64, 64, 8)])
+@pytest.mark.parametrize("cin,cout,d", [(8, 32, 48), (16, 32, 48), (32, 64, 48), (64, 64, 8)])
 def test_forward_many_tiles_against_reference(cin, cout, d):
     """Forward convolution where blocks walk several tiles (16 and 32 channels: ranges of 4
     z-planes through the ring of input planes), h is odd (the last tile's second row is
