@@ -243,26 +243,36 @@ __global__ void __launch_bounds__(64 * StagedConv<CIN>::NW, 2) conv_staged_kerne
       }
     }
     __syncthreads();
+    if (wave < P::MT) {  // wave m finalizes tile m (MT <= NW): its partial plus the others' in wave order
+      floatx16 mine = acc[0];
 #pragma unroll
-    for (int m = 0; m < P::MT; ++m) {
-      const int f = m % P::NW;
-      if (wave == f) {
-        const int y = y0 + m / P::XT, xb = x0 + (m % P::XT) * 32;
+      for (int m = 1; m < P::MT; ++m)
+        if (wave == m) mine = acc[m];
+      const int m = wave;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float sum = 0.0f;
+      for (int e = 0; e < 16; ++e) {
+        float sum = 0.0f;
 #pragma unroll
-          for (int ww = 0; ww < P::NW; ++ww)
-            sum += ww == f ? acc[m][r] : red[(m * (P::NW - 1) + (ww < f ? ww : ww - 1)) * 1024 + r * 64 + lane];
-          const int x = xb + (r / 4) * 8 + 4 * h + (r & 3);
-          if (x < W && y < H) {
-            float val = sum + bb;
+        for (int ww = 0; ww < P::NW; ++ww)
+          sum += ww == m ? mine[e] : red[(m * (P::NW - 1) + (ww < m ? ww : ww - 1)) * 1024 + e * 64 + lane];
+        mine[e] = sum;
+      }
+      const int y = y0 + m / P::XT;
+      if (y < H) {
+        int co = cout;
+        asm volatile("" : "+s"(co));  // keeps the per-element offsets from being hoisted as addresses
+        const int xb = x0 + (m % P::XT) * 32 + 4 * h;
+        const long long obase = ((nz * H + y) * (long long)W + xb) * co + co0 + c;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          if (xb + (e / 4) * 8 + (e & 3) < W) {
+            float val = mine[e] + bb;
             if (relu) val = fmaxf(val, 0.0f);
-            const long long v = (nz * H + y) * (long long)W + x;
+            const long long o = obase + ((e / 4) * 8 + (e & 3)) * co;
             if (out_f32)
-              out_f32[v * cout + co0 + c] = val;
+              out_f32[o] = val;
             else
-              out[v * cout + co0 + c] = f2bf(val);
+              out[o] = f2bf(val);
           }
         }
       }
@@ -446,18 +456,28 @@ __global__ void __launch_bounds__(256, 2) conv_ring_kernel(const uint16_t* __res
       }
       const int y = y0 + my_row;
       if (y < H) {
-        const long long vrow = ((nb * D + z) * H + y) * (long long)W;
+        // element e of the tile is voxel xb + (e / 4) * 8 + e % 4; one base per step and
+        // per-element offsets in multiples of cout (made opaque so they are not hoisted out
+        // of the z loop as 16 separate 64-bit addresses)
+        int co = cout;
+        asm volatile("" : "+s"(co));
+        const int xb = x0 + my_x + 4 * h;
+        const long long obase = (((nb * D + z) * H + y) * (long long)W + xb) * co + co0 + c;
+        if (out_f32) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int x = x0 + my_x + (e / 4) * 8 + 4 * h + (e & 3);
-          if (x < W) {
-            float val = mine[e] + bb;
-            if (relu) val = fmaxf(val, 0.0f);
-            const long long o = (vrow + x) * cout + co0 + c;
-            if (out_f32)
-              out_f32[o] = val;
-            else
-              out[o] = f2bf(val);
+          for (int e = 0; e < 16; ++e) {
+            if (xb + (e / 4) * 8 + (e & 3) < W) {
+              const float val = mine[e] + bb;
+              out_f32[obase + ((e / 4) * 8 + (e & 3)) * co] = relu ? fmaxf(val, 0.0f) : val;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            if (xb + (e / 4) * 8 + (e & 3) < W) {
+              const float val = mine[e] + bb;
+              out[obase + ((e / 4) * 8 + (e & 3)) * co] = f2bf(relu ? fmaxf(val, 0.0f) : val);
+            }
           }
         }
       }
