@@ -5,7 +5,7 @@
  *
  * All tensors are device pointers in channels-last layout, [n][d][h][w][c] with c fastest;
  * activations and weights are BF16 (uint16_t bit patterns), accumulation is FP32 on the
- * matrix cores (v_mfma_f32_32x32x8_bf16).  Convolutions are 3x3x3, stride 1, zero padding 1;
+ * matrix cores (v_mfma_f32_32x32x16_bf16).  Convolutions are 3x3x3, stride 1, zero padding 1;
  * weights are [27][cout][cin] with tap = (dz+1)*9 + (dy+1)*3 + (dx+1).  Channel counts:
  * cin in {8, 16, 32, 64, 128} for the forward convolution (a multiple of 8 for the weight
  * gradient), cout a multiple of 32.  Every call enqueues work on `stream` (a

@@ -3,11 +3,11 @@
 // the small element-wise operators of the encoder-decoder and its training.
 //
 // Convolution.  out[v][co] = sum_tap sum_ci in[v + off(tap)][ci] w[tap][co][ci] is a GEMM with
-// M = voxels, N = cout, K = 27 cin.  One wave owns 32 voxels x 32 output channels and issues
-// one v_mfma_f32_32x32x8_bf16 per (tap, 8 input channels): lane l holds the 4 input channels
-// kq..kq+3 (kq = 4 (l / 32)) of voxel l % 32 as the A fragment and the same 4 channels of
-// weight row co = l % 32 as the B fragment (both 8-byte loads in the channels-last layout);
-// the 16 accumulators of lane l are rows 8 (r / 4) + kq + r % 4, column l % 32, of the tile.
+// M = voxels, N = cout, K = 27 cin.  The kernels that carry the network (conv_ring_kernel,
+// conv_staged_kernel, wgrad_kernel) stage their operands through LDS and issue
+// v_mfma_f32_32x32x16_bf16; conv_fwd_kernel, the direct form with one wave per 32 voxels x
+// 32 output channels and v_mfma_f32_32x32x8_bf16 fed from global memory, serves channel
+// counts the others do not take (cin = 128, and planes too large for 32-bit offsets).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -54,7 +54,11 @@ constexpr int kTapOff[27][3] = {
     {0, -1, -1},  {0, -1, 0},  {0, -1, 1},  {0, 0, -1},  {0, 0, 0},  {0, 0, 1},  {0, 1, -1},  {0, 1, 0},  {0, 1, 1},
     {1, -1, -1},  {1, -1, 0},  {1, -1, 1},  {1, 0, -1},  {1, 0, 0},  {1, 0, 1},  {1, 1, -1},  {1, 1, 0},  {1, 1, 1}};
 
-// ---------------------------------------------------------------- forward convolution
+// ---------------------------------------------------------------- forward convolution, direct
+// v_mfma_f32_32x32x8_bf16: lane l holds the 4 input channels kq..kq+3 (kq = 4 (l / 32)) of
+// voxel l % 32 as the A fragment and the same 4 channels of weight row co = l % 32 as the B
+// fragment (8-byte loads in the channels-last layout); the 16 accumulators of lane l are rows
+// 8 (r / 4) + kq + r % 4, column l % 32, of the tile.
 // grid (ceil(nvox / 128), cout / (32 NT)), 256 threads: wave w of block b owns voxels
 // [(4 b + w) 32, +32) and output channels [32 NT blockIdx.y, +32 NT).  CIN is the input
 // channel count (a template constant, so the loads of a tap are issued ahead of its MFMAs);
