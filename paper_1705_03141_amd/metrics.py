@@ -89,3 +89,17 @@ def relative_errors(got: dict, ref: dict) -> dict:
     e["u"] = du / umag if umag > 0 else du
     e["umax_ref"] = umag
     return e
+
+
+def laplace_error(diag: dict, A: float, nu: float, rho_r0: float) -> dict:
+    """Laplace-law measurement of Sec. III A from the lattice's FP64 diagnostics (mean
+    pressure p_in within R/2 of the centre and p_out beyond R + 6): Delta p = p_in - p_out,
+    the radius from the red mass, R = (3 m_r / (4 pi rho_r0))^(1/3), the measured tension
+    sigma_lap = Delta p R / 2 (Eq. (lap)), the predicted sigma_th = (4/9) A (3 nu + 1/2)
+    (Eq. (sigma)) and the error E = |sigma_th - sigma_lap| / sigma_th."""
+    dp = diag["p_in"] - diag["p_out"]
+    radius = (3.0 * diag["mass_r"] / (4.0 * np.pi * rho_r0)) ** (1.0 / 3.0)
+    sigma_lap = dp * radius / 2.0
+    sigma_th = 4.0 / 9.0 * A * (3.0 * nu + 0.5)
+    return {"dp": dp, "radius": radius, "sigma_lap": sigma_lap, "sigma_th": sigma_th,
+            "E": abs(sigma_th - sigma_lap) / sigma_th}

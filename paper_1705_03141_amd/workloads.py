@@ -133,9 +133,11 @@ def _grid(x0, y0, z0, wx, wy, wz):
 def static_droplet(n: int = 32, radius: float = 8.0, rho_r0: float = 1.0, rho_b0: float = 1.0,
                    nu: float = 1.0 / 6.0, A: float = 0.01, beta: float = 0.7, width: float = 4.0,
                    center: Optional[Sequence[float]] = None, dims: Optional[Sequence[int]] = None,
-                   semi_axes: Optional[Sequence[float]] = None, steps: int = 200) -> Problem:
+                   semi_axes: Optional[Sequence[float]] = None, steps: int = 200,
+                   nu_b: Optional[float] = None) -> Problem:
     """Red droplet in blue, all faces periodic (Sec. III A).  With ``semi_axes`` the
-    droplet is the prolate spheroid of the oscillation test (Sec. III B)."""
+    droplet is the prolate spheroid of the oscillation test (Sec. III B).  ``nu`` is the
+    viscosity of both phases unless ``nu_b`` gives the blue one."""
     nx, ny, nz = dims if dims is not None else (n, n, n)
     c = center if center is not None else ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
 
@@ -151,8 +153,45 @@ def static_droplet(n: int = 32, radius: float = 8.0, rho_r0: float = 1.0, rho_b0
         t = np.tanh(2.0 * d / width)
         return 0.5 * rho_r0 * (1.0 - t), 0.5 * rho_b0 * (1.0 + t), np.zeros((3, wz, wy, wx))
 
-    return Problem(name="static_droplet", nx=nx, ny=ny, nz=nz, rho_r0=rho_r0, rho_b0=rho_b0, nu_r=nu, nu_b=nu,
-                   A=A, beta=beta, steps=steps, field_fn=fields).with_fields()
+    return Problem(name="static_droplet", nx=nx, ny=ny, nz=nz, rho_r0=rho_r0, rho_b0=rho_b0, nu_r=nu,
+                   nu_b=nu if nu_b is None else nu_b, A=A, beta=beta, steps=steps, field_fn=fields).with_fields()
+
+
+def laplace_droplet(radius: float, A: float, steps: int = 80000) -> Problem:
+    """The Laplace-law test of Sec. III A (its table of R, A and E): an 85^3 periodic
+    lattice, a red droplet of radius R at the centre in blue, interface width 4, density
+    ratio 1.5, nu = 1e-3 in both phases, no gravity, 80 000 steps.  beta = 0.7 (the paper
+    gives none)."""
+    pb = static_droplet(n=85, radius=radius, rho_r0=1.5, rho_b0=1.0, nu=1e-3, A=A, beta=0.7, width=4.0, steps=steps)
+    pb.name = f"laplace_R{radius:g}_A{A:g}"
+    return pb
+
+
+def stability_envelope(steps: int = 20000):
+    """Static droplets at the ends of the stable ranges the paper states (Sec. V): density
+    ratios gamma = rho_r / rho_b up to 1000 at nu_r = nu_b = 1e-3, and viscosity ratios
+    eta = nu_r / nu_b up to 1000 at gamma = 1.5.  48^3, R = 12, width 4, beta = 0.7, with
+    A = 1e-2 and 4e-4 (the surface tensions of Sec. III A).
+
+    The paper does not say which phase is heavy or which viscosity changes.  The blue phase
+    sets the pressure scale of the model (p = rho_b / 3 in both phases at rest), so the heavy
+    droplet is red (rho_r0 = gamma, rho_b0 = 1): a light ambient of rho_b0 = 1/gamma would
+    have a pressure below the Laplace jump at these A.  The viscosity ratio lowers the
+    blue viscosity (nu_b = 1e-3 / eta): raising nu_r to 0.1 or 1 leaves the range where the
+    printed relaxation rates are stable for a fluid at rest (about nu < 0.1)."""
+    cases = []
+    for gamma in (10.0, 100.0, 1000.0):
+        for A in (1e-2, 4e-4):
+            pb = static_droplet(n=48, radius=12.0, rho_r0=gamma, rho_b0=1.0, nu=1e-3, A=A, beta=0.7, width=4.0,
+                                steps=steps)
+            pb.name = f"envelope_gamma{gamma:g}_A{A:g}"
+            cases.append(pb)
+    for eta in (10.0, 100.0, 1000.0):
+        pb = static_droplet(n=48, radius=12.0, rho_r0=1.5, rho_b0=1.0, nu=1e-3, nu_b=1e-3 / eta, A=1e-2, beta=0.7,
+                            width=4.0, steps=steps)
+        pb.name = f"envelope_eta{eta:g}"
+        cases.append(pb)
+    return cases
 
 
 def rayleigh_taylor(width: int = 128, height: Optional[int] = None, atwood: float = 0.5, g: float = 1e-5,
