@@ -30,10 +30,12 @@ int surr_conv3d_fwd(const uint16_t *in, const uint16_t *w, const float *bias, ui
 
 /* Gradient of the input: din = conv_transpose(dout, w), i.e. the forward convolution with the
  * taps mirrored and the channel roles swapped (w_t: [27][cin][cout], made by
- * surr_conv3d_flip_weights).  cin a multiple of 32 here. */
+ * surr_conv3d_flip_weights).  cin a multiple of 32 here.  With relu_y (the ReLU output that
+ * produced the layer's input, [n][d][h][w][cin]) not NULL, din is 0 where relu_y is not
+ * positive: the gradient of the pre-activation, as surr_relu_bwd would give. */
 int surr_conv3d_flip_weights(const uint16_t *w, uint16_t *w_t, int cin, int cout, void *stream);
-int surr_conv3d_dgrad(const uint16_t *dout, const uint16_t *w_t, uint16_t *din, int n, int d, int h, int wd, int cin,
-                      int cout, void *stream);
+int surr_conv3d_dgrad(const uint16_t *dout, const uint16_t *w_t, const uint16_t *relu_y, uint16_t *din, int n, int d,
+                      int h, int wd, int cin, int cout, void *stream);
 
 /* Gradient of the weights and bias: dw[27][cout][cin] = sum_v dout[v][co] in[v + tap][ci],
  * dbias[co] = sum_v dout[v][co], FP32, reduced in a fixed order through `scratch`. */
@@ -41,7 +43,7 @@ size_t surr_conv3d_wgrad_scratch_bytes(int n, int d, int h, int wd, int cin, int
 int surr_conv3d_wgrad(const uint16_t *in, const uint16_t *dout, float *dw, float *dbias, void *scratch, int n, int d,
                       int h, int wd, int cin, int cout, void *stream);
 
-/* dx = dy where y > 0, else 0 (y: the ReLU output). count elements. */
+/* dx = dy where y > 0, else 0 (y: the ReLU output). count elements; dx may alias dy. */
 int surr_relu_bwd(const uint16_t *y, const uint16_t *dy, uint16_t *dx, long long count, void *stream);
 
 /* 2x2x2 average pooling [n][d][h][w][c] -> [n][d/2][h/2][w/2][c] (d, h, w even) and its
@@ -49,12 +51,14 @@ int surr_relu_bwd(const uint16_t *y, const uint16_t *dy, uint16_t *dx, long long
  * upsampling with an added skip tensor, out = up(in) + skip, and its gradient with respect to
  * in (the gradient of skip is dout itself); (d, h, w) are the dimensions of the coarse tensor
  * (in, din), out and skip being 2d x 2h x 2w.  c a multiple of 8 and every pointer 16-byte
- * aligned (8 channels move per access), else -1. */
+ * aligned (8 channels move per access), else -1.  surr_up_bwd with relu_y (shaped as din) not
+ * NULL gives 0 where relu_y is not positive. */
 int surr_pool_fwd(const uint16_t *in, uint16_t *out, int n, int d, int h, int wd, int c, void *stream);
 int surr_pool_bwd(const uint16_t *dout, uint16_t *din, int n, int d, int h, int wd, int c, void *stream);
 int surr_up_add_fwd(const uint16_t *in, const uint16_t *skip, uint16_t *out, int n, int d, int h, int wd, int c,
                     void *stream);
-int surr_up_bwd(const uint16_t *dout, uint16_t *din, int n, int d, int h, int wd, int c, void *stream);
+int surr_up_bwd(const uint16_t *dout, const uint16_t *relu_y, uint16_t *din, int n, int d, int h, int wd, int c,
+                void *stream);
 
 /* Mean-squared error over the first `used` of `stride` channels of pred (FP32) against
  * target (FP32, `used` channels): dpred = 2 (pred - target) / (count * used) written as
@@ -69,8 +73,10 @@ int surr_mse(const float *pred, const float *target, uint16_t *dpred, float *los
 int surr_adam(float *w, uint16_t *w_bf16, const float *g, float *m, float *v, long long count, float lr, float beta1,
               float beta2, float eps, int t, void *stream);
 
-/* out = a + b element-wise in BF16 (FP32 sum, rounded); out may alias a or b. */
-int surr_add(const uint16_t *a, const uint16_t *b, uint16_t *out, long long count, void *stream);
+/* out = a + b element-wise in BF16 (FP32 sum, rounded); out may alias a or b.  With relu_y not
+ * NULL, out is 0 where relu_y is not positive. */
+int surr_add(const uint16_t *a, const uint16_t *b, const uint16_t *relu_y, uint16_t *out, long long count,
+             void *stream);
 
 /* FP32 <-> BF16 conversion (round to nearest even). */
 int surr_to_bf16(const float *x, uint16_t *y, long long count, void *stream);

@@ -792,8 +792,9 @@ inline void launch_chunk_sums(const float* part1, float* out1, long long len1, c
 // The element-wise operators move 8 channels (16 bytes) per thread; channel counts are
 // multiples of 8 wherever they are called with voxel layouts, and the flat operators take a
 // scalar tail.
-__global__ void relu_bwd_kernel(const uint16_t* __restrict__ y, const uint16_t* __restrict__ dy,
-                                uint16_t* __restrict__ dx, long long count, int vec) {
+// dx may alias dy: each thread reads its 8 elements before writing them
+__global__ void relu_bwd_kernel(const uint16_t* __restrict__ y, const uint16_t* dy, uint16_t* dx, long long count,
+                                int vec) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long e = 8 * i;
   if (vec && e + 8 <= count) {
@@ -885,9 +886,10 @@ __global__ void up_add_kernel(const uint16_t* __restrict__ in, const uint16_t* _
   *reinterpret_cast<uint4*>(out + vf * c + ch) = pack8(a);
 }
 
-// thread = (coarse voxel, 8 channels)
-__global__ void up_bwd_kernel(const uint16_t* __restrict__ dout, uint16_t* __restrict__ din, int d, int h, int w, int c,
-                              long long count) {
+// thread = (coarse voxel, 8 channels); where mask (a ReLU output) is not positive the
+// gradient is 0
+__global__ void up_bwd_kernel(const uint16_t* __restrict__ dout, const uint16_t* __restrict__ mask,
+                              uint16_t* __restrict__ din, int d, int h, int w, int c, long long count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const int c8 = c / 8, ch = 8 * (int)(i % c8);
@@ -907,6 +909,13 @@ __global__ void up_bwd_kernel(const uint16_t* __restrict__ dout, uint16_t* __res
             f);
 #pragma unroll
     for (int j = 0; j < 8; ++j) s[j] += f[j];
+  }
+  if (mask) {
+    float mv[8];
+    unpack8(*reinterpret_cast<const uint4*>(mask + vc * c + ch), mv);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (!(mv[j] > 0.0f)) s[j] = 0.0f;
   }
   *reinterpret_cast<uint4*>(din + vc * c + ch) = pack8(s);
 }
@@ -956,8 +965,10 @@ __global__ void adam_kernel(float* __restrict__ w, uint16_t* __restrict__ wb, co
   wb[i] = f2bf(wi);
 }
 
-// out may alias a or b: each thread reads its 8 elements before writing them
-__global__ void add_kernel(const uint16_t* a, const uint16_t* b, uint16_t* out, long long count, int vec) {
+// out may alias a or b: each thread reads its 8 elements before writing them.  Where mask (a
+// ReLU output) is given and not positive the sum is 0.
+__global__ void add_kernel(const uint16_t* a, const uint16_t* b, const uint16_t* mask, uint16_t* out, long long count,
+                           int vec) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long e = 8 * i;
   if (vec && e + 8 <= count) {
@@ -966,9 +977,19 @@ __global__ void add_kernel(const uint16_t* a, const uint16_t* b, uint16_t* out, 
     unpack8(*reinterpret_cast<const uint4*>(b + e), fb);
 #pragma unroll
     for (int j = 0; j < 8; ++j) fa[j] += fb[j];
+    if (mask) {
+      float mv[8];
+      unpack8(*reinterpret_cast<const uint4*>(mask + e), mv);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (!(mv[j] > 0.0f)) fa[j] = 0.0f;
+    }
     *reinterpret_cast<uint4*>(out + e) = pack8(fa);
   } else {
-    for (long long j = e; j < count && j < e + 8; ++j) out[j] = f2bf(bf2f(a[j]) + bf2f(b[j]));
+    for (long long j = e; j < count && j < e + 8; ++j) {
+      const float v = bf2f(a[j]) + bf2f(b[j]);
+      out[j] = (mask && !(bf2f(mask[j]) > 0.0f)) ? (uint16_t)0 : f2bf(v);
+    }
   }
 }
 
@@ -999,27 +1020,29 @@ inline int done() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
 }  // namespace
 
-extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, float* out_f32,
-                               int n, int d, int h, int wd, int cin, int cout, int relu, void* stream) {
+namespace {
+int conv_dispatch(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, float* out_f32, int n, int d,
+                  int h, int wd, int cin, int cout, int relu, void* stream) {
   if (n < 1 || d < 1 || h < 1 || wd < 1 || cin < 8 || cin % 8 || cout < 32 || cout % 32 || !in || !w ||
       (!out && !out_f32))
     return -1;
   const long long nvox = (long long)n * d * h * wd;
+  const bool small_plane = (long long)h * wd * cin < (1LL << 31);
   switch (cin) {
     case 8:
-      if ((long long)h * wd * 8 < (1LL << 31))
+      if (small_plane)
         launch_ring<8>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
       else
         launch_conv<8>(in, w, bias, out, out_f32, d, h, wd, cout, relu, nvox, S(stream));
       break;
     case 16:
-      if ((long long)h * wd * 16 < (1LL << 31))
+      if (small_plane)
         launch_ring<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
       else
         launch_staged<16>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
       break;
     case 32:
-      if ((long long)h * wd * 32 < (1LL << 31))
+      if (small_plane)
         launch_ring<32>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
       else
         launch_staged<32>(in, w, bias, out, out_f32, n, d, h, wd, cout, relu, S(stream));
@@ -1030,6 +1053,12 @@ extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const floa
   }
   return done();
 }
+}  // namespace
+
+extern "C" int surr_conv3d_fwd(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, float* out_f32,
+                               int n, int d, int h, int wd, int cin, int cout, int relu, void* stream) {
+  return conv_dispatch(in, w, bias, out, out_f32, n, d, h, wd, cin, cout, relu, stream);
+}
 
 extern "C" int surr_conv3d_flip_weights(const uint16_t* w, uint16_t* w_t, int cin, int cout, void* stream) {
   if (cin < 1 || cout < 1 || !w || !w_t) return -1;
@@ -1038,10 +1067,14 @@ extern "C" int surr_conv3d_flip_weights(const uint16_t* w, uint16_t* w_t, int ci
   return done();
 }
 
-extern "C" int surr_conv3d_dgrad(const uint16_t* dout, const uint16_t* w_t, uint16_t* din, int n, int d, int h, int wd,
-                                 int cin, int cout, void* stream) {
-  // the forward convolution of dout (cout channels) with w_t gives din (cin channels)
-  return surr_conv3d_fwd(dout, w_t, nullptr, din, nullptr, n, d, h, wd, cout, cin, 0, stream);
+extern "C" int surr_conv3d_dgrad(const uint16_t* dout, const uint16_t* w_t, const uint16_t* relu_y, uint16_t* din, int n,
+                                 int d, int h, int wd, int cin, int cout, void* stream) {
+  // the forward convolution of dout (cout channels) with w_t gives din (cin channels); the
+  // ReLU mask is a pass of its own (the convolution kernels have no registers to spare for it)
+  if (!din) return -1;
+  const int rc = conv_dispatch(dout, w_t, nullptr, din, nullptr, n, d, h, wd, cout, cin, 0, stream);
+  if (rc != 0 || !relu_y) return rc;
+  return surr_relu_bwd(relu_y, din, din, (long long)n * d * h * wd * cin, stream);
 }
 
 extern "C" size_t surr_conv3d_wgrad_scratch_bytes(int n, int d, int h, int wd, int cin, int cout) {
@@ -1099,10 +1132,14 @@ extern "C" int surr_up_add_fwd(const uint16_t* in, const uint16_t* skip, uint16_
   return done();
 }
 
-extern "C" int surr_up_bwd(const uint16_t* dout, uint16_t* din, int n, int d, int h, int wd, int c, void* stream) {
-  if (n < 1 || d < 1 || h < 1 || wd < 1 || c < 8 || c % 8 || !aligned16(dout) || !aligned16(din)) return -1;
+extern "C" int surr_up_bwd(const uint16_t* dout, const uint16_t* relu_y, uint16_t* din, int n, int d, int h, int wd, int c,
+                           void* stream) {
+  if (n < 1 || d < 1 || h < 1 || wd < 1 || c < 8 || c % 8 || !aligned16(dout) || !aligned16(din) ||
+      (relu_y && !aligned16(relu_y)))
+    return -1;
   const long long count = (long long)n * d * h * wd * (c / 8);
-  hipLaunchKernelGGL(up_bwd_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), dout, din, d, h, wd, c, count);
+  hipLaunchKernelGGL(up_bwd_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), dout, relu_y, din, d, h, wd, c,
+                     count);
   return done();
 }
 
@@ -1125,11 +1162,12 @@ extern "C" int surr_adam(float* w, uint16_t* w_bf16, const float* g, float* m, f
   return done();
 }
 
-extern "C" int surr_add(const uint16_t* a, const uint16_t* b, uint16_t* out, long long count, void* stream) {
+extern "C" int surr_add(const uint16_t* a, const uint16_t* b, const uint16_t* relu_y, uint16_t* out, long long count,
+                        void* stream) {
   if (count < 0 || !a || !b || !out) return -1;
   if (count == 0) return 0;
-  const int vec = aligned16(a) && aligned16(b) && aligned16(out);
-  hipLaunchKernelGGL(add_kernel, dim3(blocks(count, 8 * 256)), dim3(256), 0, S(stream), a, b, out, count, vec);
+  const int vec = aligned16(a) && aligned16(b) && aligned16(out) && (!relu_y || aligned16(relu_y));
+  hipLaunchKernelGGL(add_kernel, dim3(blocks(count, 8 * 256)), dim3(256), 0, S(stream), a, b, relu_y, out, count, vec);
   return done();
 }
 

@@ -42,7 +42,7 @@ def _lib():
         vp, i, ll, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_float
         L.surr_conv3d_fwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, i, i, i, vp]
         L.surr_conv3d_flip_weights.argtypes = [vp, vp, i, i, vp]
-        L.surr_conv3d_dgrad.argtypes = [vp, vp, vp, i, i, i, i, i, i, vp]
+        L.surr_conv3d_dgrad.argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, vp]
         L.surr_conv3d_wgrad_scratch_bytes.argtypes = [i, i, i, i, i, i]
         L.surr_conv3d_wgrad_scratch_bytes.restype = ctypes.c_size_t
         L.surr_conv3d_wgrad.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, i, i, vp]
@@ -50,10 +50,10 @@ def _lib():
         L.surr_pool_fwd.argtypes = [vp, vp, i, i, i, i, i, vp]
         L.surr_pool_bwd.argtypes = [vp, vp, i, i, i, i, i, vp]
         L.surr_up_add_fwd.argtypes = [vp, vp, vp, i, i, i, i, i, vp]
-        L.surr_up_bwd.argtypes = [vp, vp, i, i, i, i, i, vp]
+        L.surr_up_bwd.argtypes = [vp, vp, vp, i, i, i, i, i, vp]
         L.surr_mse.argtypes = [vp, vp, vp, vp, ll, i, i, vp]
         L.surr_adam.argtypes = [vp, vp, vp, vp, vp, ll, f, f, f, f, i, vp]
-        L.surr_add.argtypes = [vp, vp, vp, ll, vp]
+        L.surr_add.argtypes = [vp, vp, vp, vp, ll, vp]
         L.surr_to_bf16.argtypes = [vp, vp, ll, vp]
         L.surr_to_f32.argtypes = [vp, vp, ll, vp]
         L.surr_pack_input.argtypes = [vp, vp, ll, i, i, vp]
@@ -86,22 +86,32 @@ class Network:
         self.stream = stream
         self.device = dev = device
         rng = np.random.default_rng(seed)
+        # Every layer's weights [27][cout][cin] and bias [cout] are views into flat buffers
+        # (FP32 master copy, BF16 copy, gradient, Adam moments), so one Adam launch updates
+        # them all; each segment is a multiple of 8 elements, which keeps the BF16 views
+        # 16-byte aligned for the convolution kernels.
+        sizes = [(27 * cout * cin, cout) for _, cin, cout in LAYERS]
+        self.nparams = total = sum(a + b for a, b in sizes)
+        flat = {k: torch.zeros(total, dtype=torch.float32, device=dev) for k in ("w", "g", "m", "v")}
+        self._flat = flat
+        self._flat_bf16 = torch.empty(total, dtype=torch.int16, device=dev)
         self.w32, self.wbf, self.wt, self.b, self.gw, self.gb, self.m, self.v = {}, {}, {}, {}, {}, {}, {}, {}
-        self.bbf = {}
-        for name, cin, cout in LAYERS:
+        off = 0
+        for (name, cin, cout), (nw, nb) in zip(LAYERS, sizes):
             std = math.sqrt(2.0 / (27 * cin))
             w0 = rng.normal(0.0, std, size=(27, cout, cin)).astype(np.float32)
             if name == "out":
                 w0 *= 0.1  # start close to "no change"
-            self.w32[name] = torch.from_numpy(w0).to(dev)
-            self.b[name] = torch.zeros(cout, dtype=torch.float32, device=dev)
-            self.wbf[name] = torch.empty((27, cout, cin), dtype=torch.int16, device=dev)
+            wv = lambda k: flat[k][off:off + nw].view(27, cout, cin)
+            bv = lambda k: flat[k][off + nw:off + nw + nb]
+            self.w32[name], self.b[name] = wv("w"), bv("w")
+            self.w32[name].copy_(torch.from_numpy(w0))
+            self.gw[name], self.gb[name] = wv("g"), bv("g")
+            self.m[name] = (wv("m"), bv("m"))
+            self.v[name] = (wv("v"), bv("v"))
+            self.wbf[name] = self._flat_bf16[off:off + nw].view(27, cout, cin)
             self.wt[name] = torch.empty((27, cin, cout), dtype=torch.int16, device=dev)
-            self.gw[name] = torch.zeros((27, cout, cin), dtype=torch.float32, device=dev)
-            self.gb[name] = torch.zeros(cout, dtype=torch.float32, device=dev)
-            self.bbf[name] = torch.empty(cout, dtype=torch.int16, device=dev)  # BF16 copy Adam writes (unused)
-            for store in (self.m, self.v):
-                store[name] = (torch.zeros_like(self.w32[name]), torch.zeros_like(self.b[name]))
+            off += nw + nb
         self._refresh_bf16()
         self.act: Dict[str, "torch.Tensor"] = {}
         self.grad: Dict[str, "torch.Tensor"] = {}
@@ -118,6 +128,7 @@ class Network:
         self.g_full32 = [torch.empty(full + (32,), dtype=torch.int16, device=dev) for _ in range(3)]
         self.g_half64 = [torch.empty(half + (64,), dtype=torch.int16, device=dev) for _ in range(2)]
         self.g_half32 = torch.empty(half + (32,), dtype=torch.int16, device=dev)
+        self.g_half32b = torch.empty(half + (32,), dtype=torch.int16, device=dev)
         self.g_quarter64 = [torch.empty(quarter + (64,), dtype=torch.int16, device=dev) for _ in range(2)]
         L = _lib()
         sc = max(L.surr_conv3d_wgrad_scratch_bytes(n, d, h, w, cin, cout) for _, cin, cout in LAYERS)
@@ -184,9 +195,9 @@ class Network:
         self._conv(A["d1"], "out", None, full, relu=False, out_f32=self.y)
         return self.y
 
-    def _dgrad(self, dout, name, din, dims):
+    def _dgrad(self, dout, name, din, dims, relu_y=None):
         _, cin, cout = next(l for l in LAYERS if l[0] == name)
-        _ok(_lib().surr_conv3d_dgrad(_p(dout), _p(self.wt[name]), _p(din), *dims, cin, cout, self.stream),
+        _ok(_lib().surr_conv3d_dgrad(_p(dout), _p(self.wt[name]), _p(relu_y), _p(din), *dims, cin, cout, self.stream),
             f"dgrad {name}")
 
     def _wgrad(self, inp, dout, name, dims):
@@ -194,46 +205,38 @@ class Network:
         _ok(_lib().surr_conv3d_wgrad(_p(inp), _p(dout), _p(self.gw[name]), _p(self.gb[name]), _p(self.scratch), *dims,
                                      cin, cout, self.stream), f"wgrad {name}")
 
-    def _relu_bwd(self, y, dy, dx):
-        _ok(_lib().surr_relu_bwd(_p(y), _p(dy), _p(dx), y.numel(), self.stream), "relu_bwd")
-
-    def _add(self, a, b, out):
-        _ok(_lib().surr_add(_p(a), _p(b), _p(out), a.numel(), self.stream), "add")
+    def _add(self, a, b, out, relu_y=None):
+        _ok(_lib().surr_add(_p(a), _p(b), _p(relu_y), _p(out), a.numel(), self.stream), "add")
 
     def backward(self, dy):
-        """dy: BF16 gradient of the loss with respect to the 32-channel output."""
+        """dy: BF16 gradient of the loss with respect to the 32-channel output.  Each ReLU's
+        gradient is applied by the operator that produces the gradient of its output (data
+        gradient, upsampling gradient or the skip addition)."""
         L = _lib()
         n, d, h, w = self.shape
         full, half, quarter = (n, d, h, w), (n, d // 2, h // 2, w // 2), (n, d // 4, h // 4, w // 4)
         A = self.act
         g0, g1, g2 = self.g_full32
-        self._wgrad(A["d1"], dy, "out", full)
-        self._dgrad(dy, "out", g0, full)
-        self._relu_bwd(A["d1"], g0, g1)                      # g1 = d(d1 pre-activation)
-        self._wgrad(A["u1"], g1, "d1", full)
-        self._dgrad(g1, "d1", g2, full)                      # g2 = d(u1) = d(e1 skip) + up-part
-        _ok(L.surr_up_bwd(_p(g2), _p(self.g_half32), *half, 32, self.stream), "up1_bwd")  # d(d2)
         h0, h1 = self.g_half64
-        dd2 = self.torch.empty_like(self.g_half32)
-        self._relu_bwd(A["d2"], self.g_half32, dd2)
-        self._wgrad(A["u2"], dd2, "d2", half)
-        self._dgrad(dd2, "d2", h0, half)                     # h0 = d(u2)
         q0, q1 = self.g_quarter64
-        _ok(L.surr_up_bwd(_p(h0), _p(q0), *quarter, 64, self.stream), "up2_bwd")
-        self._relu_bwd(A["bt"], q0, q1)
-        self._wgrad(A["p2"], q1, "bt", quarter)
-        self._dgrad(q1, "bt", q0, quarter)                   # d(p2)
+        self._wgrad(A["d1"], dy, "out", full)
+        self._dgrad(dy, "out", g1, full, relu_y=A["d1"])      # g1 = d(d1 pre-activation)
+        self._wgrad(A["u1"], g1, "d1", full)
+        self._dgrad(g1, "d1", g2, full)                        # g2 = d(u1) = d(e1 skip) + up-part
+        _ok(L.surr_up_bwd(_p(g2), _p(A["d2"]), _p(self.g_half32b), *half, 32, self.stream), "up1_bwd")
+        self._wgrad(A["u2"], self.g_half32b, "d2", half)       # g_half32b = d(d2 pre-activation)
+        self._dgrad(self.g_half32b, "d2", h0, half)            # h0 = d(u2)
+        _ok(L.surr_up_bwd(_p(h0), _p(A["bt"]), _p(q1), *quarter, 64, self.stream), "up2_bwd")
+        self._wgrad(A["p2"], q1, "bt", quarter)                # q1 = d(bt pre-activation)
+        self._dgrad(q1, "bt", q0, quarter)                     # d(p2)
         _ok(L.surr_pool_bwd(_p(q0), _p(h1), *half, 64, self.stream), "pool2_bwd")
-        self._add(h1, h0, h1)                                 # d(e2) = pool part + skip part
-        self._relu_bwd(A["e2"], h1, h0)
-        self._wgrad(A["p1"], h0, "e2", half)
-        self._dgrad(h0, "e2", self.g_half32, half)           # d(p1)
+        self._add(h1, h0, h1, relu_y=A["e2"])                  # d(e2 pre-activation): pool part + skip part
+        self._wgrad(A["p1"], h1, "e2", half)
+        self._dgrad(h1, "e2", self.g_half32, half)             # d(p1)
         _ok(L.surr_pool_bwd(_p(self.g_half32), _p(g0), *full, 32, self.stream), "pool1_bwd")
-        self._add(g0, g2, g0)                                 # d(e1)
-        self._relu_bwd(A["e1"], g0, g1)
-        self._wgrad(A["e1a"], g1, "e1b", full)
-        self._dgrad(g1, "e1b", g0, full)
-        self._relu_bwd(A["e1a"], g0, g1)
+        self._add(g0, g2, g0, relu_y=A["e1"])                  # d(e1 pre-activation)
+        self._wgrad(A["e1a"], g0, "e1b", full)
+        self._dgrad(g0, "e1b", g1, full, relu_y=A["e1a"])      # d(e1a pre-activation)
         self._wgrad(A["x"], g1, "e1a", full)
 
     def loss_and_grad(self, target, sync: bool = True):
@@ -250,15 +253,14 @@ class Network:
         return float(self.loss_part.cpu().numpy().astype(np.float64).sum()) / (nv * FIELDS)
 
     def adam_step(self, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step over every weight and bias (one launch over the flat buffers), then
+        the mirrored weights of the data gradient."""
         self.t += 1
         L = _lib()
+        f = self._flat
+        _ok(L.surr_adam(_p(f["w"]), _p(self._flat_bf16), _p(f["g"]), _p(f["m"]), _p(f["v"]), self.nparams, self.lr,
+                        beta1, beta2, eps, self.t, self.stream), "adam")
         for name, cin, cout in LAYERS:
-            mw, mb = self.m[name]
-            vw, vb = self.v[name]
-            _ok(L.surr_adam(_p(self.w32[name]), _p(self.wbf[name]), _p(self.gw[name]), _p(mw), _p(vw),
-                            self.w32[name].numel(), self.lr, beta1, beta2, eps, self.t, self.stream), "adam w")
-            _ok(L.surr_adam(_p(self.b[name]), _p(self.bbf[name]), _p(self.gb[name]), _p(mb), _p(vb), cout, self.lr, beta1, beta2,
-                            eps, self.t, self.stream), "adam b")
             _ok(L.surr_conv3d_flip_weights(_p(self.wbf[name]), _p(self.wt[name]), cin, cout, self.stream), "flip")
 
     def train_step(self, x, target, sync_loss: bool = True):

@@ -78,10 +78,15 @@ def test_conv_operators_against_reference(cin, cout):
         w_t = torch.empty((27, cin, cout), dtype=torch.int16, device="cuda")
         assert L.surr_conv3d_flip_weights(S._p(wd), S._p(w_t), cin, cout, None) == 0
         din = torch.empty((n, d, h, w, cin), dtype=torch.int16, device="cuda")
-        assert L.surr_conv3d_dgrad(S._p(doutd), S._p(w_t), S._p(din), n, d, h, w, cin, cout, None) == 0
-        e_dg = rel(from_dev_bf16(din), R.conv3d_dgrad(dout, wt))
-        msg += f" dgrad {e_dg:.2e}"
-        assert e_dg < 1e-2
+        assert L.surr_conv3d_dgrad(S._p(doutd), S._p(w_t), None, S._p(din), n, d, h, w, cin, cout, None) == 0
+        ref_dg = R.conv3d_dgrad(dout, wt)
+        e_dg = rel(from_dev_bf16(din), ref_dg)
+        # with a ReLU output as mask: zero exactly where it is not positive
+        assert L.surr_conv3d_dgrad(S._p(doutd), S._p(w_t), S._p(xd), S._p(din), n, d, h, w, cin, cout, None) == 0
+        got_m = from_dev_bf16(din)
+        e_dgm = rel(got_m, np.where(x > 0, ref_dg, 0.0))
+        msg += f" dgrad {e_dg:.2e} masked {e_dgm:.2e}"
+        assert e_dg < 1e-2 and e_dgm < 1e-2 and not got_m[x <= 0].any()
     log(msg)
     assert e_fwd < 1e-5 and e_wg < 1e-5 and e_bg < 1e-5
 
@@ -185,8 +190,11 @@ def test_elementwise_operators_against_reference():
     assert np.array_equal(from_dev_bf16(out_f), bf16_round(R.pool_bwd(coarse)))
     assert L.surr_up_add_fwd(S._p(cd), S._p(fd), S._p(out_f), n, d // 2, h // 2, w // 2, c, None) == 0
     assert rel(from_dev_bf16(out_f), bf16_round(R.up(coarse) + fine)) < 4e-3
-    assert L.surr_up_bwd(S._p(fd), S._p(out_c), n, d // 2, h // 2, w // 2, c, None) == 0
+    assert L.surr_up_bwd(S._p(fd), None, S._p(out_c), n, d // 2, h // 2, w // 2, c, None) == 0
     assert rel(from_dev_bf16(out_c), bf16_round(R.up_bwd(fine))) < 4e-3
+    assert L.surr_up_bwd(S._p(fd), S._p(cd), S._p(out_c), n, d // 2, h // 2, w // 2, c, None) == 0
+    got = from_dev_bf16(out_c)
+    assert rel(got, bf16_round(np.where(coarse > 0, R.up_bwd(fine), 0.0))) < 4e-3 and not got[coarse <= 0].any()
     assert L.surr_pool_fwd(S._p(fd), S._p(out_c), n, d, h, w, 12, None) == -1  # channels not a multiple of 8
     # flat operators: a ragged count, then a pointer off the 16-byte grid (scalar path)
     count = fine.size - 5
@@ -199,10 +207,18 @@ def test_elementwise_operators_against_reference():
     assert np.array_equal(got[:count], want[:count]) and not got[count:].any()
     flat_a, flat_b = fd.view(-1), gd.view(-1)
     o = torch.zeros_like(flat_a)
-    assert L.surr_add(S._p(flat_a[1:]), S._p(flat_b[1:]), S._p(o[1:]), count, None) == 0
+    assert L.surr_add(S._p(flat_a[1:]), S._p(flat_b[1:]), None, S._p(o[1:]), count, None) == 0
     ref = bf16_round(y[1:count + 1] + np.resize(g, fine.size)[1:count + 1])
     got = from_dev_bf16(o)
     assert rel(got[1:count + 1], ref) < 4e-3 and got[0] == 0 and not got[count + 1:].any()
+    # with a mask, on the vector path (aligned, ragged count) and on the scalar path
+    mask = np.resize(g, fine.size)
+    for off in (0, 1):
+        o.zero_()
+        assert L.surr_add(S._p(flat_a[off:]), S._p(flat_b[off:]), S._p(flat_b[off:]), S._p(o[off:]), count, None) == 0
+        got = from_dev_bf16(o)[off:off + count]
+        want = np.where(mask[off:off + count] > 0, y[off:off + count] + mask[off:off + count], 0.0)
+        assert rel(got, bf16_round(want)) < 4e-3 and not got[mask[off:off + count] <= 0].any()
     # input packing and the squared error
     nv = n * d * h * w
     x4 = rng.normal(size=(nv, 4)).astype(np.float32)

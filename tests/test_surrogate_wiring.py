@@ -54,8 +54,17 @@ class StandIn:
         _store_bf16(wt, ww[::-1].transpose(0, 2, 1))
         return 0
 
-    def surr_conv3d_dgrad(self, dout, wt, din, n, d, h, wd, cin, cout, stream):
-        return self.surr_conv3d_fwd(dout, wt, None, din, None, n, d, h, wd, cout, cin, 0, stream)
+    def surr_conv3d_dgrad(self, dout, wt, relu_y, din, n, d, h, wd, cin, cout, stream):
+        self.surr_conv3d_fwd(dout, wt, None, din, None, n, d, h, wd, cout, cin, 0, stream)
+        if relu_y is not None:
+            self._mask(relu_y, din, n * d * h * wd * cin, "dgrad relu_y")
+        return 0
+
+    def _mask(self, y, x, count, what):
+        _need(y, count, what)
+        _need(x, count, what + " (gradient)")
+        g = _f32_of_bf16(x)[:count] * (_f32_of_bf16(y)[:count] > 0)
+        _store_bf16(x, g)
 
     def surr_conv3d_wgrad_scratch_bytes(self, n, d, h, wd, cin, cout):
         return 4
@@ -103,11 +112,13 @@ class StandIn:
         _store_bf16(out, R.up(x) + s)
         return 0
 
-    def surr_up_bwd(self, dout, din, n, d, h, wd, c, stream):
+    def surr_up_bwd(self, dout, relu_y, din, n, d, h, wd, c, stream):
         _need(dout, 8 * n * d * h * wd * c, "up_bwd dout")
         _need(din, n * d * h * wd * c, "up_bwd din")
         g = _f32_of_bf16(dout)[: 8 * n * d * h * wd * c].reshape(n, 2 * d, 2 * h, 2 * wd, c)
         _store_bf16(din, R.up_bwd(g))
+        if relu_y is not None:
+            self._mask(relu_y, din, n * d * h * wd * c, "up_bwd relu_y")
         return 0
 
     def surr_mse(self, pred, target, dpred, loss_part, count, stride, used, stream):
@@ -137,10 +148,12 @@ class StandIn:
         _store_bf16(wb, ww)
         return 0
 
-    def surr_add(self, a, b, out, count, stream):
+    def surr_add(self, a, b, relu_y, out, count, stream):
         for x, nm in ((a, "a"), (b, "b"), (out, "out")):
             _need(x, count, "add " + nm)
         _store_bf16(out, _f32_of_bf16(a)[:count] + _f32_of_bf16(b)[:count])
+        if relu_y is not None:
+            self._mask(relu_y, out, count, "add relu_y")
         return 0
 
     def surr_to_bf16(self, x, y, count, stream):
