@@ -998,14 +998,23 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict
   if (i < count) y[i] = f2bf(x[i]);
 }
 
-// y[v][c] = bf16(x[v][c]) for c < c_src, 0 for c_src <= c < c_dst
-__global__ void pack_input_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, long long count, int c_src,
-                                  int c_dst) {
+// y[v][c] = bf16(x[v][c]) for c < c_src, 0 for c_src <= c < c_dst; thread = (voxel, 8
+// output channels), with 16-byte stores when c_dst is a multiple of 8 and y is aligned
+__global__ void pack_input_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, long long nvox, int c_src,
+                                  int c_dst, int vec) {
+  const int g8 = (c_dst + 7) / 8;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const long long v = i / c_dst;
-  const int c = (int)(i % c_dst);
-  y[i] = c < c_src ? f2bf(x[v * c_src + c]) : (uint16_t)0;
+  if (i >= nvox * g8) return;
+  const long long v = i / g8;
+  const int c0 = 8 * (int)(i % g8);
+  float f[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) f[j] = c0 + j < c_src ? x[v * c_src + c0 + j] : 0.0f;
+  if (vec) {
+    *reinterpret_cast<uint4*>(y + v * c_dst + c0) = pack8(f);
+  } else {
+    for (int j = 0; j < 8 && c0 + j < c_dst; ++j) y[v * c_dst + c0 + j] = f2bf(f[j]);
+  }
 }
 
 __global__ void to_f32_kernel(const uint16_t* __restrict__ x, float* __restrict__ y, long long count) {
@@ -1185,8 +1194,9 @@ extern "C" int surr_to_f32(const uint16_t* x, float* y, long long count, void* s
 
 extern "C" int surr_pack_input(const float* x, uint16_t* y, long long nvox, int c_src, int c_dst, void* stream) {
   if (nvox < 0 || c_src < 1 || c_dst < c_src || !x || !y) return -1;
-  const long long count = nvox * c_dst;
-  if (count == 0) return 0;
-  hipLaunchKernelGGL(pack_input_kernel, dim3(blocks(count, 256)), dim3(256), 0, S(stream), x, y, count, c_src, c_dst);
+  if (nvox == 0) return 0;
+  const int vec = c_dst % 8 == 0 && aligned16(y);
+  hipLaunchKernelGGL(pack_input_kernel, dim3(blocks(nvox * ((c_dst + 7) / 8), 256)), dim3(256), 0, S(stream), x, y, nvox,
+                     c_src, c_dst, vec);
   return done();
 }
