@@ -523,9 +523,21 @@ struct BatchGroup {
   int nblocks = 0;
 };
 
+// The outlet or the inflow work of the cases of one storage type, launched once per step:
+// device tables of per-case arguments for parity 0 and 1 and block offsets over each plane.
+struct AuxGroup {
+  int storage = 0;
+  std::vector<int> cases;
+  AuxArgs* d_aux[2] = {nullptr, nullptr};     // outlet groups
+  StepArgs* d_step[2] = {nullptr, nullptr};   // inflow groups
+  int* d_first = nullptr;
+  int nblocks = 0;
+};
+
 struct lbm_batch {
   std::vector<lbm_ctx*> c;
   std::vector<BatchGroup> groups;
+  std::vector<AuxGroup> outlets, inflows;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
@@ -544,6 +556,16 @@ static void free_groups(lbm_batch* b) {
     if (g.d_first) (void)hipFree(g.d_first);
   }
   b->groups.clear();
+  for (auto* v : {&b->outlets, &b->inflows}) {
+    for (auto& g : *v) {
+      for (int k = 0; k < 2; ++k) {
+        if (g.d_aux[k]) (void)hipFree(g.d_aux[k]);
+        if (g.d_step[k]) (void)hipFree(g.d_step[k]);
+      }
+      if (g.d_first) (void)hipFree(g.d_first);
+    }
+    v->clear();
+  }
 }
 
 extern "C" void lbm_batch_destroy(lbm_batch* b) {
@@ -654,6 +676,61 @@ static lbm_status build_groups(lbm_batch* b) {
          hipMemcpy(g.d_first, first.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return batch_fail(b, LBM_ENOMEM, "batch table allocation failed");
   }
+  // outlet and inflow work per storage type (an outflow lattice's record shares its parity)
+  for (int k = 0; k < (int)b->c.size(); ++k) {
+    const lbm_ctx* c = b->c[k];
+    for (int which = 0; which < 2; ++which) {
+      const bool has = which == 0 ? c->geo.face_hi == FACE_OUTFLOW : (bool)c->geo.inflow;
+      if (!has) continue;
+      auto& v = which == 0 ? b->outlets : b->inflows;
+      AuxGroup* g = nullptr;
+      for (auto& x : v)
+        if (x.storage == (int)c->p.storage) g = &x;
+      if (!g) {
+        v.emplace_back();
+        g = &v.back();
+        g->storage = (int)c->p.storage;
+      }
+      g->cases.push_back(k);
+    }
+  }
+  for (int which = 0; which < 2; ++which)
+    for (auto& g : which == 0 ? b->outlets : b->inflows) {
+      const int n = (int)g.cases.size();
+      std::vector<int> first(n + 1, 0);
+      std::vector<AuxArgs> ha[2];
+      std::vector<StepArgs> hs[2];
+      for (int j = 0; j < n; ++j) {
+        lbm_ctx* c = b->c[g.cases[j]];
+        first[j + 1] = first[j] + (int)((c->geo.plane + 255) / 256);
+        for (int par = 0; par < 2; ++par) {
+          if (which == 0) {
+            AuxArgs a = aux_args(c);
+            a.g_in = c->g[par];
+            a.sc_in = c->sc[par];
+            a.outlet_in = c->outlet[par];
+            a.outlet_out = c->outlet[1 - par];
+            ha[par].push_back(a);
+          } else {
+            StepArgs st{};
+            fill_step_args(c, par, par, st);
+            hs[par].push_back(st);
+          }
+        }
+      }
+      g.nblocks = first[n];
+      bool ok = hipMalloc((void**)&g.d_first, (n + 1) * sizeof(int)) == hipSuccess &&
+                hipMemcpy(g.d_first, first.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+      for (int par = 0; par < 2 && ok; ++par) {
+        if (which == 0)
+          ok = hipMalloc((void**)&g.d_aux[par], n * sizeof(AuxArgs)) == hipSuccess &&
+               hipMemcpy(g.d_aux[par], ha[par].data(), n * sizeof(AuxArgs), hipMemcpyHostToDevice) == hipSuccess;
+        else
+          ok = hipMalloc((void**)&g.d_step[par], n * sizeof(StepArgs)) == hipSuccess &&
+               hipMemcpy(g.d_step[par], hs[par].data(), n * sizeof(StepArgs), hipMemcpyHostToDevice) == hipSuccess;
+      }
+      if (!ok) return batch_fail(b, LBM_ENOMEM, "batch table allocation failed");
+    }
   return LBM_OK;
 }
 
@@ -674,24 +751,24 @@ extern "C" lbm_status lbm_batch_step(lbm_batch* b, int nsteps) {
   if (hipEventRecord(b->ev0, b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "event record failed");
   for (int k = 0; k < nsteps; ++k) {
     const int par = b->c[0]->cur;
-    const bool init = b->c[0]->step == 0;
-    for (lbm_ctx* c : b->c)
-      if (c->geo.face_hi == FACE_OUTFLOW) {
-        const hipError_t e = launch_outlet((int)c->p.storage, aux_args(c), b->stream);
-        if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("outlet kernel: ") + hipGetErrorString(e));
-      }
+    const long long step = b->c[0]->step;
+    const bool init = step == 0;
+    for (const auto& g : b->outlets) {
+      const hipError_t e =
+          launch_batch_outlet(g.storage, g.d_aux[par], g.d_first, (int)g.cases.size(), g.nblocks, step, b->stream);
+      if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("outlet kernel: ") + hipGetErrorString(e));
+    }
     for (const auto& g : b->groups) {
       const hipError_t e = launch_batch(g.storage, g.d_args[par], g.d_first, (int)g.cases.size(), g.nblocks, init,
                                         g.tx, g.ty, b->stream);
       if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("batch step kernel: ") + hipGetErrorString(e));
     }
+    for (const auto& g : b->inflows) {
+      const hipError_t e =
+          launch_batch_inflow(g.storage, g.d_step[par], g.d_first, (int)g.cases.size(), g.nblocks, step, b->stream);
+      if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("inflow kernel: ") + hipGetErrorString(e));
+    }
     for (lbm_ctx* c : b->c) {
-      if (c->geo.inflow) {
-        StepArgs s{};
-        fill_step_args(c, c->cur, c->out_cur, s);
-        const hipError_t e = launch_inflow((int)c->p.storage, s, b->stream);
-        if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("inflow kernel: ") + hipGetErrorString(e));
-      }
       c->cur = 1 - c->cur;
       if (c->geo.face_hi == FACE_OUTFLOW) c->out_cur = 1 - c->out_cur;
       c->step++;

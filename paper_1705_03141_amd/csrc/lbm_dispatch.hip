@@ -54,6 +54,26 @@ hipError_t launch_outlet(int storage, const AuxArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_batch_outlet(int storage, const AuxArgs* cases, const int* first, int ncases, int nblocks,
+                               long long step, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_batch_outlet_T<float>(cases, first, ncases, nblocks, step, s);
+    case 1: return launch_batch_outlet_T<_Float16>(cases, first, ncases, nblocks, step, s);
+    case 2: return launch_batch_outlet_T<bf16>(cases, first, ncases, nblocks, step, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_inflow(int storage, const StepArgs* cases, const int* first, int ncases, int nblocks,
+                               long long step, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_batch_inflow_T<float>(cases, first, ncases, nblocks, step, s);
+    case 1: return launch_batch_inflow_T<_Float16>(cases, first, ncases, nblocks, step, s);
+    case 2: return launch_batch_inflow_T<bf16>(cases, first, ncases, nblocks, step, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_fields(int storage, const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
                          hipStream_t s) {
   switch (storage) {

@@ -68,6 +68,12 @@ int step_resident_blocks_T(int tx, int ty, int device);
 template <typename T>
 hipError_t launch_outlet_T(const AuxArgs& a, hipStream_t s);
 template <typename T>
+hipError_t launch_batch_outlet_T(const AuxArgs* cases, const int* first, int ncases, int nblocks, long long step,
+                                 hipStream_t s);
+template <typename T>
+hipError_t launch_batch_inflow_T(const StepArgs* cases, const int* first, int ncases, int nblocks, long long step,
+                                 hipStream_t s);
+template <typename T>
 hipError_t launch_fields_T(const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_populations_T(const AuxArgs& a, double* out, hipStream_t s);
@@ -88,6 +94,14 @@ hipError_t launch_inflow(int storage, const StepArgs& a, hipStream_t s);
 // Workgroups of the step kernel that fit on the device at once (0 if unknown).
 int step_resident_blocks(int storage, int tx, int ty, int device);
 hipError_t launch_outlet(int storage, const AuxArgs& a, hipStream_t s);
+// The outlet records, and the inflow planes, of several lattices of one storage type at one
+// step in one launch: cases (device array of ncases argument blocks of the step's parity),
+// first (device, ncases + 1 block offsets of 256-thread blocks over each plane),
+// nblocks = first[ncases].
+hipError_t launch_batch_outlet(int storage, const AuxArgs* cases, const int* first, int ncases, int nblocks,
+                               long long step, hipStream_t s);
+hipError_t launch_batch_inflow(int storage, const StepArgs* cases, const int* first, int ncases, int nblocks,
+                               long long step, hipStream_t s);
 hipError_t launch_fields(int storage, const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
                          hipStream_t s);
 hipError_t launch_populations(int storage, const AuxArgs& a, double* out, hipStream_t s);

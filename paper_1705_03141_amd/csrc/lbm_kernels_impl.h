@@ -323,10 +323,9 @@ __device__ void outlet_state(const AuxArgs& A, int x, int y, float (&dr)[Q], flo
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) outlet_kernel(const AuxArgs A) {
+__device__ __forceinline__ void outlet_body(const AuxArgs& A, const int col) {
   const Geo& G = A.geo;
   const int plane = G.plane;
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= plane) return;
   float dr[Q], db[Q], e, psi;
   outlet_state<T>(A, col % G.nx, col / G.nx, dr, db, e, psi);
@@ -337,6 +336,31 @@ __global__ void __launch_bounds__(256) outlet_kernel(const AuxArgs A) {
   }
   A.outlet_out[54 * plane + col] = e;
   A.outlet_out[55 * plane + col] = psi;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) outlet_kernel(const AuxArgs A) {
+  outlet_body<T>(A, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+}
+
+// The outlets of many lattices in one launch: case c owns blocks [first[c], first[c+1]);
+// every case of a batch is at the same step, which is passed in.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    batch_outlet_kernel(const AuxArgs* __restrict__ cases, const int* __restrict__ first, int ncases, long long step) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = ncases;  // first[lo] <= b < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  AuxArgs A = cases[lo];
+  A.step = step;
+  A.init_mode = step == 0 ? 1 : 0;
+  outlet_body<T>(A, (b - first[lo]) * 256 + (int)threadIdx.x);
 }
 
 // Densities, momentum sum_i f_i c_i and (optionally) per-colour pre-collision populations of
@@ -539,6 +563,13 @@ hipError_t launch_outlet_T(const AuxArgs& a, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_batch_outlet_T(const AuxArgs* cases, const int* first, int ncases, int nblocks, long long step,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(batch_outlet_kernel<T>, dim3((unsigned)nblocks), dim3(256), 0, s, cases, first, ncases, step);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_fields_T(const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
                            hipStream_t s) {
   const long long nb = (long long)wx * wy * wz;
@@ -565,6 +596,7 @@ hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, lon
 
 #define LBM_INSTANTIATE_STORAGE(T)                                                                                \
   template hipError_t launch_outlet_T<T>(const AuxArgs&, hipStream_t);                                            \
+  template hipError_t launch_batch_outlet_T<T>(const AuxArgs*, const int*, int, int, long long, hipStream_t);                                            \
   template hipError_t launch_fields_T<T>(const AuxArgs&, int, int, int, int, int, int, double*, hipStream_t);    \
   template hipError_t launch_populations_T<T>(const AuxArgs&, double*, hipStream_t);                              \
   template hipError_t launch_diag_T<T>(const AuxArgs&, const DiagQuery&, double*, long long, double*, hipStream_t);

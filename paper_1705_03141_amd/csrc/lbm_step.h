@@ -493,9 +493,8 @@ __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU)
 // Inflow sites (R10) after a step: each emits the red equilibrium at rho_r0 and u_in(1 + eps xi)
 // e_z with Phi = 0 and no blue; the step kernel collided them like any cell.
 template <typename T>
-__global__ void __launch_bounds__(256) inflow_kernel(const StepArgs A) {
+__device__ __forceinline__ void inflow_body(const StepArgs& A, const int col, const long long step) {
   const Geo& G = A.geo;
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= G.plane) return;
   const int x = col % G.nx, y = col / G.nx;
   if (!is_inflow(G, x, y, 0)) return;
@@ -503,7 +502,7 @@ __global__ void __launch_bounds__(256) inflow_kernel(const StepArgs A) {
   const rsrc_t gslab = buffer_of(A.g_out, (unsigned)(Q * pb));
   const rsrc_t sslab = buffer_of(A.sc_out, (unsigned)(5 * G.plane * 4));
   const unsigned colT = (unsigned)(col * (int)sizeof(T)), col4 = (unsigned)(col * 4);
-  const float u = inflow_speed(G, (long long)col, A.step);
+  const float u = inflow_speed(G, (long long)col, step);
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     Word<T>::store(Word<T>::enc(eq_dev<i>(G.rho_r0, 0.0f, 0.0f, u)), gslab, colT, i * pb);
@@ -513,6 +512,28 @@ __global__ void __launch_bounds__(256) inflow_kernel(const StepArgs A) {
   store_f32(0.0f, sslab, col4, 2 * G.plane * 4);
   store_f32(0.0f, sslab, col4, 3 * G.plane * 4);
   store_f32(0.0f, sslab, col4, 4 * G.plane * 4);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) inflow_kernel(const StepArgs A) {
+  inflow_body<T>(A, (int)(blockIdx.x * blockDim.x + threadIdx.x), A.step);
+}
+
+// The inflow planes of many lattices in one launch (case c owns blocks [first[c],
+// first[c+1]); every case of a batch is at the same step, which is passed in).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    batch_inflow_kernel(const StepArgs* __restrict__ cases, const int* __restrict__ first, int ncases, long long step) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = ncases;  // first[lo] <= b < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  inflow_body<T>(cases[lo], (b - first[lo]) * 256 + (int)threadIdx.x, step);
 }
 
 // ================================================================== launchers
@@ -576,6 +597,13 @@ hipError_t launch_inflow_T(const StepArgs& a, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_batch_inflow_T(const StepArgs* cases, const int* first, int ncases, int nblocks, long long step,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(batch_inflow_kernel<T>, dim3((unsigned)nblocks), dim3(256), 0, s, cases, first, ncases, step);
+  return hipGetLastError();
+}
+
+template <typename T>
 int step_resident_blocks_T(int tx, int ty, int device) {
   if (tx == 32 && ty == 4) return resident_tile<T, 32, 4>(device);
   if (tx == 32 && ty == 8) return resident_tile<T, 32, 8>(device);
@@ -588,7 +616,8 @@ int step_resident_blocks_T(int tx, int ty, int device) {
 #define LBM_INSTANTIATE_STEP(T)                                                 \
   template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t); \
   template hipError_t launch_batch_T<T>(const StepArgs*, const int*, int, int, bool, int, int, hipStream_t); \
-  template hipError_t launch_inflow_T<T>(const StepArgs&, hipStream_t);          \
+  template hipError_t launch_inflow_T<T>(const StepArgs&, hipStream_t);                                         \
+  template hipError_t launch_batch_inflow_T<T>(const StepArgs*, const int*, int, int, long long, hipStream_t);          \
   template int step_resident_blocks_T<T>(int, int, int);
 
 }  // namespace lbm
