@@ -301,7 +301,19 @@ def test_training_on_lattice_trajectories_beats_persistence():
     for _ in range(10):
         net_te.predict(te[4])
     t_net = (time.perf_counter() - t1) / 10
+    # the gain: the same horizon on the lattice (both held-out cases in one batch)
+    bat = lbm.Batch(held)
+    bat.step(1)
+    bat.sync()
+    t2 = time.perf_counter()
+    bat.step(horizon)
+    bat.sync()
+    t_lbm_h = time.perf_counter() - t2
+    bat.close()
     log(f"[surrogate] judge: interface error per held-out case {np.round(ierr, 3).tolist()} coarse cells, "
-        f"surrogate kept {use.tolist()}; one prediction {t_net * 1e3:.2f} ms for {horizon} steps of 2 cases")
+        f"surrogate kept {use.tolist()}; one prediction {t_net * 1e3:.2f} ms for {horizon} steps of 2 cases "
+        f"(host arrays in and out), the lattice {t_lbm_h * 1e3:.2f} ms: {t_lbm_h / t_net:.0f}x")
     assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:20])
     assert err_trained < persistence and err_trained < err_untrained
+    assert use.all()
+    assert t_net < t_lbm_h / 5
