@@ -103,3 +103,31 @@ def laplace_error(diag: dict, A: float, nu: float, rho_r0: float) -> dict:
     sigma_th = 4.0 / 9.0 * A * (3.0 * nu + 0.5)
     return {"dp": dp, "radius": radius, "sigma_lap": sigma_lap, "sigma_th": sigma_th,
             "E": abs(sigma_th - sigma_lap) / sigma_th}
+
+
+def extrema_times(ts, values) -> list:
+    """Times of the interior local extrema of a sampled signal, each refined by the vertex of
+    the parabola through it and its two neighbours (uniform sampling)."""
+    ts = np.asarray(ts, dtype=float)
+    v = np.asarray(values, dtype=float)
+    out = []
+    for k in range(1, len(v) - 1):
+        if (v[k] - v[k - 1]) * (v[k + 1] - v[k]) < 0:
+            den = v[k - 1] - 2.0 * v[k] + v[k + 1]
+            off = 0.5 * (v[k - 1] - v[k + 1]) / den if den != 0 else 0.0
+            out.append(float(ts[k] + off * (ts[1] - ts[0])))
+    return out
+
+
+def oscillation_period(ts, values, skip: int = 1) -> float:
+    """Period of a decaying oscillation: twice the mean time between successive extrema,
+    leaving out the first ``skip`` half-periods (the largest, least linear amplitude); NaN
+    when fewer than skip + 1 half-periods were seen."""
+    e = extrema_times(ts, values)
+    halves = np.diff(e)[skip:]
+    return float(2.0 * halves.mean()) if len(halves) else float("nan")
+
+
+def equivalent_radius(phi: np.ndarray) -> float:
+    """Radius of the sphere with the volume of the cells where phi > 0 (the droplet)."""
+    return float((3.0 * float((np.asarray(phi) > 0).sum()) / (4.0 * np.pi)) ** (1.0 / 3.0))

@@ -157,6 +157,17 @@ def static_droplet(n: int = 32, radius: float = 8.0, rho_r0: float = 1.0, rho_b0
                    nu_b=nu if nu_b is None else nu_b, A=A, beta=beta, steps=steps, field_fn=fields).with_fields()
 
 
+def oscillating_droplet(nu: float, A: float, steps: int = 10000) -> Problem:
+    """The oscillation test of Sec. III B: a 41^3 periodic lattice with a prolate spheroid of
+    semi-axes 15, 11, 11 at the centre, density ratio 4 (the red droplet rho_r0 = 1 in
+    rho_b0 = 0.25, reading R19), nu in both phases, the printed relaxation rates, beta = 0.7."""
+    pb = static_droplet(n=41, rho_r0=1.0, rho_b0=0.25, nu=nu, A=A, beta=0.7, semi_axes=(15.0, 11.0, 11.0),
+                        steps=steps)
+    pb.s = None
+    pb.name = f"oscillating_nu{nu:g}_A{A:g}"
+    return pb
+
+
 def laplace_droplet(radius: float, A: float, steps: int = 80000) -> Problem:
     """The Laplace-law test of Sec. III A (its table of R, A and E): an 85^3 periodic
     lattice, a red droplet of radius R at the centre in blue, interface width 4, density

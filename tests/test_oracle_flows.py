@@ -37,13 +37,15 @@ def test_lamb_oscillation_period(O):
     """41^3, prolate spheroid with semi-axes 15, 11, 11 at the centre, density ratio 4
     (droplet rho = 1 in rho = 0.25, reading R19), nu = 3.333e-3 in both, A = 1e-2, Suga's
     rates (Table II, first row).  The x extent starts at its maximum; twice the time to its
-    first minimum is compared with T = 2 pi / omega_2 of Eqs. (resoFreq), (Lamb).
+    first minimum is compared with T = 2 pi / omega_2 of Eqs. (resoFreq), (Lamb), with R_e
+    the equivalent radius of the droplet (reading R27: the volume where phi > 0, here taken
+    at that minimum).
 
-    Loose pin: this oracle's period comes out ~24 % longer than the formula here, ~15 % for
-    the same droplet scaled by 1.5 on 61^3, and ~13 % at density ratio 1: the gap shrinks
-    with resolution, while the paper reports 0.6 % at 41^3 with set-up details (box walls,
-    interface width, definition of R_e) that it does not give.  30 % still fails a surface
-    tension off by a factor 2 or a wrong sign in the perturbation."""
+    The first half-period has the largest, least linear amplitude (semi-axes 15 against 11),
+    which lengthens it by a few percent; the GPU test of all Table II rows measures the
+    later oscillations and lands within the paper's errors.  Measured here: 5.9 %.  10 %
+    fails a surface tension off by a factor 1.5 either way (T scales as sigma^(-1/2): errors
+    of 13 % and 30 %) or a wrong sign in the perturbation."""
     nu, A = 3.333e-3, 1.0e-2
     rho1, rho2 = 1.0, 0.25
     pb = W.static_droplet(n=41, rho_r0=rho1, rho_b0=rho2, nu=nu, A=A, beta=0.7, semi_axes=(15.0, 11.0, 11.0))
@@ -51,35 +53,41 @@ def test_lamb_oscillation_period(O):
     o = O.Oracle(pb)
     tau = 3.0 * nu + 0.5
     sigma = 4.0 / 9.0 * A * tau
-    Re = (15.0 * 11.0 * 11.0) ** (1.0 / 3.0)
     n = 2
-    w_star = math.sqrt(n * (n + 1) * (n - 1) * (n + 2) * sigma / (Re ** 3 * (n * rho2 + (n + 1) * rho1)))
-    mu1, mu2 = rho1 * nu, rho2 * nu
-    chi = ((2 * n + 1) ** 2 * math.sqrt(mu1 * mu2 * rho1 * rho2)
-           / (math.sqrt(2.0) * Re * (n * rho2 + (n + 1) * rho1) * (math.sqrt(mu1 * rho1) + math.sqrt(mu2 * rho2))))
-    omega = w_star - 0.5 * chi * math.sqrt(w_star) + 0.25 * chi * chi
-    T_th = 2 * math.pi / omega
+
+    def lamb_period(Re):
+        w_star = math.sqrt(n * (n + 1) * (n - 1) * (n + 2) * sigma / (Re ** 3 * (n * rho2 + (n + 1) * rho1)))
+        mu1, mu2 = rho1 * nu, rho2 * nu
+        chi = ((2 * n + 1) ** 2 * math.sqrt(mu1 * mu2 * rho1 * rho2)
+               / (math.sqrt(2.0) * Re * (n * rho2 + (n + 1) * rho1) * (math.sqrt(mu1 * rho1) + math.sqrt(mu2 * rho2))))
+        omega = w_star - 0.5 * chi * math.sqrt(w_star) + 0.25 * chi * chi
+        return 2 * math.pi / omega
+
     # half-length of the droplet along x through its centre: where phi crosses 0
     c = 20
-    every, total = 25, int(0.75 * T_th)
-    ts, ext = [], []
+    every, total = 25, int(0.75 * lamb_period(13.5))
+    ts, ext, vols = [], [], []
     for step in range(0, total + 1, every):
         if step:
             o.step(every)
-        phi = o.fields()["phi"][c, c, :]
+        phi3 = o.fields()["phi"]
+        phi = phi3[c, c, :]
         k = c
         while k + 1 < pb.nx and phi[k + 1] > 0:
             k += 1
         ts.append(step)
         ext.append(k + phi[k] / (phi[k] - phi[k + 1]) - c)
+        vols.append(float((phi3 > 0).sum()))
     ts, ext = np.array(ts, float), np.array(ext)
     kmin = int(np.argmin(ext))
     assert 0 < kmin < len(ext) - 1, "no minimum of the x extent"
     t_min = _extremum_time(ts, ext, kmin, "min")
     T_sim = 2.0 * t_min
+    Re = (3.0 * vols[kmin] / (4.0 * math.pi)) ** (1.0 / 3.0)
+    T_th = lamb_period(Re)
     err = abs(T_sim - T_th) / T_th
-    print(f"T_th {T_th:.1f}  T_sim {T_sim:.1f}  error {100 * err:.1f} %")
-    assert err < 0.30, (T_sim, T_th)
+    print(f"R_e {Re:.3f}  T_th {T_th:.1f}  T_sim {T_sim:.1f}  error {100 * err:.1f} %")
+    assert err < 0.10, (T_sim, T_th)
 
 
 def test_free_slip_channel_has_no_wall_friction(O):
