@@ -601,62 +601,61 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
   for (int k = 0; k < 9; ++k) acc[k] = floatx16{};
   float bsum = 0.0f;  // wave 0, lane (h, c): channel co0 + c over voxels x0 + 32 h .. + 31
 
-  // 16-byte chunks this thread moves: dout^T item t + 192 k -> (voxel x0 + it / 4, channels
-  // co0 + 8 (it % 4) ..); in^T item lane + 64 k -> (voxel x0 - 8 + it / 4, channels ci0 + 8 (it % 4) ..)
-  constexpr int PB = (4 * kRowB + 63) / 64;
-  auto load_dout = [&](long long nz, int y, int x0, uint4 (&buf)[2]) {
+  // 16-byte chunks this thread moves, two voxels at a time so that the transposed stores are
+  // whole dwords (one channel of both voxels, paired by v_perm): dout^T item it = t
+  // (it < 128) -> voxels x0 + 2 (it / 4) + {0, 1}, channels co0 + 8 (it % 4) ..; in^T item
+  // lane + 64 k -> voxels x0 - 8 + 2 ((lane + 64 k) / 4) + {0, 1}, channels ci0 + 8 ((lane + 64 k) % 4) ..
+  constexpr int PB = (2 * kRowB + 63) / 64;  // voxel-pair items per lane of a source row
+  auto pair_store = [&](uint16_t* base, int stride, int q, int xi, const uint4& A, const uint4& B) {
+    const uint32_t a4[4] = {A.x, A.y, A.z, A.w}, b4[4] = {B.x, B.y, B.z, B.w};
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int it = t + 192 * k;
-      buf[k] = make_uint4(0, 0, 0, 0);
-      const int x = x0 + (it >> 2);
-      if (it < 256 && x < W)
-        buf[k] = *reinterpret_cast<const uint4*>(dout + ((nz * H + y) * (long long)W + x) * cout + co0 + 8 * (it & 3));
+    for (int k = 0; k < 4; ++k) {
+      *reinterpret_cast<uint32_t*>(base + trow(8 * q + 2 * k, stride) + xi) = __builtin_amdgcn_perm(b4[k], a4[k], 0x05040100u);
+      *reinterpret_cast<uint32_t*>(base + trow(8 * q + 2 * k + 1, stride) + xi) =
+          __builtin_amdgcn_perm(b4[k], a4[k], 0x07060302u);
+    }
+  };
+  auto load_dout = [&](long long nz, int y, int x0, uint4 (&buf)[2]) {
+    buf[0] = buf[1] = make_uint4(0, 0, 0, 0);
+    if (t < 128) {
+      const int q = t & 3, x = x0 + 2 * (t >> 2);
+      const uint16_t* src = dout + ((nz * H + y) * (long long)W + x) * cout + co0 + 8 * q;
+      if (x < W) buf[0] = *reinterpret_cast<const uint4*>(src);
+      if (x + 1 < W) buf[1] = *reinterpret_cast<const uint4*>(src + cout);
     }
   };
   auto store_dout = [&](const uint4 (&buf)[2]) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int it = t + 192 * k;
-      if (it < 256) {
-        const int q = it & 3, xi = it >> 2;
-        const uint32_t wv[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) sA[trow(8 * q + i, kRsA) + xi] = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
-      }
-    }
+    if (t < 128) pair_store(sA, kRsA, t & 3, 2 * (t >> 2), buf[0], buf[1]);
   };
-  auto load_row = [&](long long nz, int z, int yy, int x0, uint4 (&buf)[PB]) {
+  auto load_row = [&](long long nz, int z, int yy, int x0, uint4 (&buf)[PB][2]) {
     const int zz = z + dz;
     const bool row_ok = zz >= 0 && zz < D && yy >= 0 && yy < H;
     const long long base = ((nz + dz) * H + yy) * (long long)W;
 #pragma unroll
     for (int k = 0; k < PB; ++k) {
       const int it = lane + 64 * k;
-      const int q = it & 3, x = x0 - 8 + (it >> 2);
-      buf[k] = make_uint4(0, 0, 0, 0);
-      if (it < 4 * kRowB && row_ok && x >= 0 && x < W && ci0 + 8 * q < cin)
-        buf[k] = *reinterpret_cast<const uint4*>(in + (base + x) * cin + ci0 + 8 * q);
+      const int q = it & 3, x = x0 - 8 + 2 * (it >> 2);
+      buf[k][0] = buf[k][1] = make_uint4(0, 0, 0, 0);
+      if (it < 2 * kRowB && row_ok && ci0 + 8 * q < cin) {
+        const uint16_t* src = in + (base + x) * cin + ci0 + 8 * q;
+        if (x >= 0 && x < W) buf[k][0] = *reinterpret_cast<const uint4*>(src);
+        if (x + 1 >= 0 && x + 1 < W) buf[k][1] = *reinterpret_cast<const uint4*>(src + cin);
+      }
     }
   };
-  auto store_row = [&](int yy, const uint4 (&buf)[PB]) {
+  auto store_row = [&](int yy, const uint4 (&buf)[PB][2]) {
     uint16_t* dst = sB[wave][(yy + 3) % 3];
 #pragma unroll
     for (int k = 0; k < PB; ++k) {
       const int it = lane + 64 * k;
-      if (it < 4 * kRowB) {
-        const int q = it & 3, xi = it >> 2;
-        const uint32_t wv[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) dst[trow(8 * q + i, kRsB) + xi] = (uint16_t)(wv[i >> 1] >> (16 * (i & 1)));
-      }
+      if (it < 2 * kRowB) pair_store(dst, kRsB, it & 3, 2 * (it >> 2), buf[k][0], buf[k][1]);
     }
   };
 
   // a segment continues the previous one's column when it is the next y of the same
   // (n, z, segment); its dout row and its one new source row are then loaded during the
   // previous segment's MFMAs
-  uint4 pfa[2], pfb[PB];
+  uint4 pfa[2], pfb[PB][2];
   bool have = false;
   long long prev_col = -1;
   int prev_y = -2;
@@ -680,7 +679,7 @@ __global__ void __launch_bounds__(192, 2) wgrad_kernel(const uint16_t* __restric
       load_dout(nz, y, x0, tb);
       store_dout(tb);
       for (int yy = cont ? y + 1 : y - 1; yy <= y + 1; ++yy) {
-        uint4 rb[PB];
+        uint4 rb[PB][2];
         load_row(nz, z, yy, x0, rb);
         store_row(yy, rb);
       }
