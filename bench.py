@@ -34,7 +34,7 @@ PEAK_GBS = 8000.0
 # HBM bytes per step-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
 # scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000); valid
 # only for the kernel sources they were taken on.
-COUNTERS = {"sources_sha16": "5b8de3e1b573ee07", "storage": "f32", "fetch_kib": 579095.0, "fetch_scale": 2.0,
+COUNTERS = {"sources_sha16": "17dd3425c15b51e0", "storage": "f32", "fetch_kib": 579288.7, "fetch_scale": 2.0,
             "write_kib": 1048576.0, "write_scale": 1.0}
 KERNEL_SOURCES = ["csrc/lbm_cell.h", "csrc/lbm_device.h", "csrc/lbm_kernels.h", "csrc/lbm_kernels_impl.h",
                   "csrc/lbm_step.h", "csrc/lbm_storage_f32.hip", "build.py"]

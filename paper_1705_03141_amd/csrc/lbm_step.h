@@ -7,12 +7,13 @@
 // of a cell needs the densities of time t of its 26 neighbours, so the 2(TX+2)+2TY cells of
 // the ring around the column are pulled as well (densities only), each by one of the first
 // threads.  Per plane counter p the workgroup
-//   1. loads the scalars (e, psi, w) of source plane p+2 with a 2-cell halo and issues the 27
+//   1. loads the scalars (e, psi, w) of source plane p+3 with a 2-cell halo and issues the 27
 //      population loads of the cells of plane p+1 (and of its ring cells) into registers,
-//   2. writes the scalars, decoded into (e, a, b, w), into an LDS ring of 3 planes; barrier,
+//   2. writes the scalars, decoded into (e, a, b, w), into an LDS ring of 4 planes (the pull
+//      reads planes p..p+2, stored before the previous barrier),
 //   3. completes the pull of plane p+1 (the population loads have been in flight since 1)
-//      and writes rho_r/rho, rho_b/rho and rho of its cells and ring into an LDS ring of 3
-//      planes; barrier,
+//      and writes rho_r/rho, rho_b/rho and rho of its cells and ring into an LDS ring of 4
+//      planes; barrier (the only one per plane),
 //   4. collides plane p with the gradient taken from the density ring, and stores 27
 //      deviations + 5 scalars per cell.
 // The deviations of plane p+1 stay in registers until step 4 of the next plane.
@@ -242,9 +243,14 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   using Tile = StepTile<TX, TY>;
   constexpr int NT = Tile::kThreads, NR = Tile::kRing, SX = Tile::SX, NS = Tile::kStaged, DX = Tile::DX,
                 ND = Tile::kDense, KS = Tile::kStagePerThread;
-  __shared__ float4 sS[3][NS];  // staged scalars (e, a, b, w_x) of 3 source planes
-  __shared__ float2 sW[3][NS];  // (w_y, w_z)
-  __shared__ float4 sD[3][ND];  // (rho_r/rho, rho_b/rho, rho) of time t of 3 planes, 1-cell ring
+  // Four slots each, so that one barrier per plane suffices: the scalars of plane p+3 are
+  // staged while planes p..p+2 are read (their slot held p-1, last read before the previous
+  // barrier), and the densities of plane p+1 are written while planes p-1..p+1 are read by
+  // the collision (their slot held p-3, last read two barriers earlier).
+  __shared__ float4 sS[4][NS];  // staged scalars (e, a, b, w_x) of source planes
+  __shared__ float2 sW[4][NS];  // (w_y, w_z)
+  __shared__ float4 sD[4][ND];  // (rho_r/rho, rho_b/rho, rho) of time t, 1-cell ring
+  auto slot4 = [](int q) { return q & 3; };
 
   const Geo& G = A.geo;
   const bool zper = G.face_lo == FACE_PERIODIC;
@@ -303,7 +309,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
         for (int c = 0; c < 5; ++c) st[k][c] = load_f32(r, stOff[k], c * plane * 4);
   };
   auto stage_store = [&](int q) {
-    const int s = slot3(q);
+    const int s = slot4(q);
 #pragma unroll
     for (int k = 0; k < KS; ++k)
       if (k < KS - 1 || tid + k * NT < NS) {
@@ -322,7 +328,10 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
     stage_store(z0 - 2);
     stage_load(z0 - 1);
     stage_store(z0 - 1);
+    stage_load(z0);
+    stage_store(z0);
   }
+  __syncthreads();
 
   // one pass: pull plane p+1 into nxt, collide plane p from cur
   auto pass = [&](const int p, PlaneState& cur, PlaneState& nxt) {
@@ -333,8 +342,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
     const bool loads_q = !INIT && pull_q && !outlet_q;
     const int mode = plane_mode(G, zq);
 
-    // 1. scalars of plane p+2, then the populations of plane p+1
-    if constexpr (!INIT) stage_load(p + 2);
+    // 1. scalars of plane p+3, then the populations of plane p+1
+    if constexpr (!INIT) stage_load(p + 3);
     __builtin_amdgcn_sched_barrier(0);
     typename Word<T>::W ldI[Q], ldR[Q];
     if (loads_q) {
@@ -353,9 +362,9 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
       });
     }
     __builtin_amdgcn_sched_barrier(0);
-    // 2. staged scalars to LDS
-    if constexpr (!INIT) stage_store(p + 2);
-    __syncthreads();
+    // 2. staged scalars to LDS (planes p..p+2, which the pull reads, were stored in earlier
+    // passes, before the last barrier)
+    if constexpr (!INIT) stage_store(p + 3);
 
     // 3. complete the pull of plane q: own cell (with deviations) and ring cell (densities).
     // The LDS bases are made opaque per pass so that the compiler does not hoist one address
@@ -364,9 +373,9 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
     asm volatile("" : "+v"(bI), "+v"(bR));
     if (!pull_q) nxt.clear();
     if (pull_q) {
-      const int s = slot3(q);
-      const float4* S[3] = {sS[slot3(q - 1)], sS[s], sS[slot3(q + 1)]};
-      const float2* W[3] = {sW[slot3(q - 1)], sW[s], sW[slot3(q + 1)]};
+      const int s = slot4(q);
+      const float4* S[3] = {sS[slot4(q - 1)], sS[s], sS[slot4(q + 1)]};
+      const float2* W[3] = {sW[slot4(q - 1)], sW[s], sW[slot4(q + 1)]};
       // the ring first: its loads are the older ones and its registers are freed sooner
       if (ringer) {
         float r_rho, r_r, r_b, r_e, r_sh, r_dr, r_df[Q];
@@ -415,9 +424,9 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
       const rsrc_t sslab = buffer_of(A.sc_out + (size_t)p * 5 * (size_t)plane, sc_bytes);
       // (inflow sites are collided like any cell here; inflow_kernel overwrites them)
       {
-        const int sm = (!zper && p == 0) ? slot3(p) : slot3(p - 1);
-        const int sp = (!zper && p == G.nz - 1) ? slot3(p) : slot3(p + 1);
-        const int s0 = slot3(p);
+        const int sm = (!zper && p == 0) ? slot4(p) : slot4(p - 1);
+        const int sp = (!zper && p == G.nz - 1) ? slot4(p) : slot4(p + 1);
+        const int s0 = slot4(p);
         // grad phi from the cell's minority colour fraction t (phi = 2a - 1 = 1 - 2b): near a
         // pure phase phi = -1 + 2a carries only the absolute precision of 1 in FP32, while a
         // itself keeps its relative precision, so the direction of grad phi stays defined
