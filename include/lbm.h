@@ -72,6 +72,13 @@ typedef struct {
   lbm_storage storage;
 } lbm_params;
 
+/* Interfacial tension of the perturbation operator, Eq. (sigma): sigma = (4/9) A tau in
+ * lattice units, tau = 3 nu + 1/2 the relaxation time of the fluid whose viscosity nu is
+ * given (at a jet's interface, the continuous phase's).  lbm_A_from_sigma inverts it.  Pure
+ * host arithmetic; NaN for nu <= 0 or a negative A / sigma. */
+double lbm_sigma_from_A(double A, double nu);
+double lbm_A_from_sigma(double sigma, double nu);
+
 /* Create a context: validates the parameters, allocates the device state (two copies of
  * 27 populations plus 5 per-cell scalars per cell) and uploads the constants.  No kernel
  * runs.  hip_stream is a hipStream_t or NULL.  On success *out owns the device memory. */

@@ -136,6 +136,16 @@ static lbm_status check_params(const lbm_params* p, lbm_ctx* c, std::string& msg
   return LBM_OK;
 }
 
+extern "C" double lbm_sigma_from_A(double A, double nu) {
+  if (!(nu > 0.0) || !(A >= 0.0)) return NAN;
+  return 4.0 / 9.0 * A * (3.0 * nu + 0.5);
+}
+
+extern "C" double lbm_A_from_sigma(double sigma, double nu) {
+  if (!(nu > 0.0) || !(sigma >= 0.0)) return NAN;
+  return 9.0 * sigma / (4.0 * (3.0 * nu + 0.5));
+}
+
 extern "C" lbm_status lbm_create(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   if (!params || !out) return fail(nullptr, LBM_EINVAL, "null argument");
   *out = nullptr;

@@ -97,6 +97,9 @@ def library():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_selftest_collide_host.argtypes = [P, _D, _D, _D, _D, _D, _D]
+        for name in ("lbm_sigma_from_A", "lbm_A_from_sigma"):
+            getattr(L, name).argtypes = [ctypes.c_double, ctypes.c_double]
+            getattr(L, name).restype = ctypes.c_double
         L.lbm_batch_create.argtypes = [P, ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.lbm_batch_case.argtypes = [vp, ctypes.c_int]
         L.lbm_batch_case.restype = vp
@@ -125,7 +128,7 @@ def header_functions():
     """Names of the functions declared in include/lbm.h."""
     with open(HEADER) as fh:
         text = fh.read()
-    return sorted(set(re.findall(r"^\s*(?:[a-z_]+\s+)+\**\s*(lbm_[a-z_0-9]+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:[a-z_]+\s+)+\**\s*(lbm_[A-Za-z_0-9]+)\s*\(", text, re.M)))
 
 
 def _ptr(a):
@@ -345,6 +348,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def sigma_from_A(A: float, nu: float) -> float:
+    """Interfacial tension of the perturbation operator, Eq. (sigma), for the fluid of
+    viscosity nu (lbm_sigma_from_A)."""
+    return float(library().lbm_sigma_from_A(float(A), float(nu)))
+
+
+def A_from_sigma(sigma: float, nu: float) -> float:
+    """Surface-tension parameter giving the interfacial tension sigma, Eq. (sigma)
+    inverted (lbm_A_from_sigma)."""
+    return float(library().lbm_A_from_sigma(float(sigma), float(nu)))
 
 
 def selftest_collide_host(problem, fr, fb, grad_phi, grad_rho):

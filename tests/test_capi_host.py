@@ -112,3 +112,22 @@ def test_host_collision_matches_oracle(oracle_lib, case):
         worst = max(worst, np.abs(got_r - want_r).max() / scale, np.abs(got_b - want_b).max() / scale)
     # FP32 arithmetic on deviations, values rebuilt around O(1) rest equilibria
     assert worst < 2e-6, worst
+
+
+def test_sigma_helpers_match_table2(L):
+    """The library's Eq. (sigma) helpers reproduce the interfacial tension the paper lists for
+    every (nu, A) pair of its oscillating-droplet table (three significant digits), and
+    lbm_A_from_sigma inverts lbm_sigma_from_A."""
+    import math
+    import os
+    import numpy as np
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table2_oscillating_droplet.txt"))
+    for nu, A, sigma, _ in rows:
+        s = lbm.sigma_from_A(A, nu)
+        assert abs(s - sigma) <= 0.006 * sigma, (nu, A, s, sigma)
+        assert abs(lbm.A_from_sigma(s, nu) - A) <= 1e-15 * A
+    # the jet workload's surface-tension parameter is the same conversion at the continuous phase
+    pb = W.jet(nx=32, ny=32, nz=64, diameter=8.0, u_in=0.04, weber=220.0, fields=False)
+    sigma_we = pb.rho_r0 * 0.04 ** 2 * 8.0 / 220.0   # We = rho_j u^2 D / sigma, Eq. (jetWeber)
+    assert abs(lbm.sigma_from_A(pb.A, pb.nu_b) - sigma_we) <= 1e-12 * sigma_we
+    assert math.isnan(lbm.sigma_from_A(1e-2, 0.0)) and math.isnan(lbm.A_from_sigma(-1.0, 0.1))
