@@ -46,11 +46,13 @@ def state_bytes(storage: str) -> float:
     return 2.0 * (27 * elem + 5 * 4)
 
 
-def run_gpu(pb, storage, steps, warmup):
+def run_gpu(pb, storage, steps, warmup, autotune=True):
     import torch
     from paper_1705_03141_amd import lbm
 
     lat = lbm.Lattice(pb, storage=storage)
+    if autotune:
+        lat.autotune(trial_steps=30)  # tile shape timed on a scratch lattice, outside the timed region
     lat.step(warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -61,6 +63,7 @@ def run_gpu(pb, storage, steps, warmup):
     wall = time.perf_counter() - t0
     kernel_ms = lat.last_step_kernel_ms()
     diag = lat.diagnostics()
+    diag["tiling"] = lat.tiling()
     lat.close()
     return wall, kernel_ms, diag
 
@@ -240,6 +243,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default tile shape instead of timing them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--sweep", action="store_true",
@@ -273,8 +277,8 @@ def main():
     pb = W.cfg_rayleigh_taylor()
     n = pb.ncells
     log(f"{pb.name} {pb.nx}x{pb.ny}x{pb.nz}, storage {args.storage}, {args.warmup}+{args.steps} steps")
-    wall, kernel_ms, diag = run_gpu(pb, args.storage, args.steps, args.warmup)
-    log(f"{wall * 1e3 / args.steps:.3f} ms/step wall, kernel {kernel_ms:.3f} ms")
+    wall, kernel_ms, diag = run_gpu(pb, args.storage, args.steps, args.warmup, not args.no_autotune)
+    log(f"{wall * 1e3 / args.steps:.3f} ms/step wall, kernel {kernel_ms:.3f} ms, tiling {diag['tiling']}")
     if diag["unstable"]:
         print("bench.py: the run went unstable", file=sys.stderr)
         sys.exit(1)
@@ -284,7 +288,7 @@ def main():
              "state_traffic_frac": state_bytes(args.storage) * n / (kernel_ms * 1e-3) / 1e9 / PEAK_GBS}
     for st in ("f16", "bf16"):
         if st != args.storage and not args.no_extra:
-            w2, k2, _ = run_gpu(pb, st, max(args.steps // 2, 10), args.warmup)
+            w2, k2, _ = run_gpu(pb, st, max(args.steps // 2, 10), args.warmup, not args.no_autotune)
             log(f"storage {st}: kernel {k2:.3f} ms")
             extra[f"{st}_mlups"] = n * max(args.steps // 2, 10) / w2 / 1e6
     line = {
@@ -301,7 +305,8 @@ def main():
         "dtype": "f32" if args.storage == "f32" else f"f32 compute, {args.storage} storage",
         "data": "synthetic",
         "config": {"workload": "rayleigh_taylor_128x128x512", "nx": pb.nx, "ny": pb.ny, "nz": pb.nz,
-                   "atwood": 0.5, "g": 1e-5, "reynolds": 256, "storage": args.storage},
+                   "atwood": 0.5, "g": 1e-5, "reynolds": 256, "storage": args.storage,
+                   "tile": list(diag["tiling"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_GBS, "traffic": measured_traffic(args.storage)},
         "extra": extra,

@@ -100,10 +100,22 @@ lbm_status lbm_set_inflow(lbm_ctx *ctx, double xc, double yc, double diameter, d
 
 /* Tile shape of the step kernel: (tx, ty) in {(32, 4), (32, 8), (32, 16), (64, 4), (64, 8)} cells per workgroup,
  * zchunk >= 1 z planes per workgroup, or 0 to let the library choose it from the number of
- * workgroups the device holds at once.  Default: (64, 4, 0) for FP32 storage with nx >= 64,
- * (32, 8, 0) otherwise.  Results do not depend on the
+ * workgroups the device holds at once.  Default: (64, 4, 0) for nx >= 64, (32, 8, 0)
+ * otherwise.  Results do not depend on the
  * tiling; this is a tuning hook.  LBM_EINVAL for other shapes or zchunk < 0. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int tx, int ty, int zchunk);
+
+/* Time each supported tile shape (32x8, 64x4, 32x4) for trial_steps steps on a scratch
+ * lattice with this context's parameters (blue fluid at rest; it needs the device memory of
+ * a second lattice of this size while it runs) and keep the fastest for lbm_step.  The
+ * context's state is not touched and results do not depend on the choice.  LBM_EINVAL for
+ * trial_steps < 1; allocation or device errors as lbm_create / lbm_step. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int trial_steps);
+
+/* The tile shape lbm_step uses: (tx, ty) and the z chunk.  A value not yet chosen (by
+ * lbm_set_tiling, lbm_autotune or the first lbm_step) reads 0.  LBM_EINVAL for a NULL
+ * argument. */
+lbm_status lbm_get_tiling(const lbm_ctx *ctx, int *tx, int *ty, int *zchunk);
 
 /* Enqueue nsteps time steps (nsteps >= 0) on the context's stream; returns at once. */
 lbm_status lbm_step(lbm_ctx *ctx, int nsteps);

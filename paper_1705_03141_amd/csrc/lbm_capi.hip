@@ -296,8 +296,9 @@ static int auto_zchunk(const lbm_ctx* c) {
 
 static void choose_tiling(lbm_ctx* c) {
   if (c->tx == 0) {
-    // measured on MI355X: 64 x 4 tiles for FP32 state on rows of 64 cells or more, 32 x 8 otherwise
-    const bool wide = c->p.storage == LBM_F32 && c->geo.nx >= 64;
+    // measured on MI355X: 64 x 4 tiles on rows of 64 cells or more, 32 x 8 otherwise
+    // (lbm_autotune times the shapes for a given lattice)
+    const bool wide = c->geo.nx >= 64;
     c->tx = wide ? 64 : 32;
     c->ty = wide ? 4 : 8;
   }
@@ -634,7 +635,7 @@ static void batch_tiling(lbm_batch* b) {
   (void)hipGetDevice(&dev);
   for (lbm_ctx* c : b->c) {
     if (c->tx == 0) {
-      const bool wide = c->p.storage == LBM_F32 && c->geo.nx >= 64;
+      const bool wide = c->geo.nx >= 64;
       c->tx = wide ? 64 : 32;
       c->ty = wide ? 4 : 8;
     }
@@ -807,12 +808,70 @@ extern "C" double lbm_batch_last_step_ms(const lbm_batch* cb) {
   return b->last_ms;
 }
 
-// Autotuner: for each distinct (lattice shape, storage) of the batch, time every supported
-// tile shape on a scratch lattice of that shape (blue fluid at rest, the case's physics) for
-// trial_steps steps and keep the fastest.  The cases' own states are not touched.
+// Time every supported tile shape on a scratch lattice with the parameters of c (blue fluid
+// at rest) for trial_steps steps each, on `stream`, and return the fastest in (tx, ty).  c's
+// own state is not touched.
+static lbm_status time_tile_shapes(const lbm_ctx* c, void* stream, int trial_steps, int& tx, int& ty,
+                                   std::string& err) {
+  static const int shapes[][2] = {{32, 8}, {64, 4}, {32, 4}};
+  lbm_ctx* t = nullptr;
+  lbm_status st = lbm_create(&c->p, stream, &t);
+  if (st != LBM_OK) {
+    err = g_create_error;
+    return st;
+  }
+  const size_t n = (size_t)c->geo.n;
+  std::vector<double> rr(n, 0.0), rb(n, c->p.rho_b0);
+  st = lbm_init_fields(t, rr.data(), rb.data(), nullptr);
+  double best = -1.0;
+  tx = 32;
+  ty = 8;
+  for (const auto& sh : shapes) {
+    if (st != LBM_OK) break;
+    if ((st = lbm_set_tiling(t, sh[0], sh[1], 0)) != LBM_OK) break;
+    t->zchunk = 0;
+    if ((st = lbm_step(t, 1)) != LBM_OK || (st = lbm_step(t, trial_steps)) != LBM_OK) break;
+    const double ms = lbm_last_step_kernel_ms(t);
+    if (ms <= 0.0) {
+      st = LBM_EDEVICE;
+      t->err = "no kernel time recorded";
+      break;
+    }
+    if (best < 0.0 || ms < best) {
+      best = ms;
+      tx = sh[0];
+      ty = sh[1];
+    }
+  }
+  err = t->err;
+  lbm_destroy(t);
+  return st;
+}
+
+extern "C" lbm_status lbm_autotune(lbm_ctx* c, int trial_steps) {
+  if (!c) return LBM_EINVAL;
+  if (trial_steps < 1) return fail(c, LBM_EINVAL, "trial_steps must be >= 1");
+  int tx = 0, ty = 0;
+  std::string err;
+  const lbm_status st = time_tile_shapes(c, c->stream, trial_steps, tx, ty, err);
+  if (st != LBM_OK) return fail(c, st, "autotune: " + err);
+  c->tx = tx;
+  c->ty = ty;
+  c->zchunk = 0;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_tiling(const lbm_ctx* c, int* tx, int* ty, int* zchunk) {
+  if (!c || !tx || !ty || !zchunk) return LBM_EINVAL;
+  *tx = c->tx;
+  *ty = c->ty;
+  *zchunk = c->zchunk;
+  return LBM_OK;
+}
+
+// Autotuner of a batch: one timing per distinct (lattice shape, storage) of the batch.
 extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps) {
   if (!b || trial_steps < 1) return LBM_EINVAL;
-  static const int shapes[][2] = {{32, 8}, {64, 4}, {32, 4}};
   struct Pick {
     int nx, ny, nz, storage, tx, ty;
   };
@@ -823,33 +882,10 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps) {
     for (const Pick& p : picks)
       if (p.nx == G.nx && p.ny == G.ny && p.nz == G.nz && p.storage == (int)c->p.storage) found = &p;
     if (!found) {
-      lbm_ctx* t = nullptr;
-      lbm_status st = lbm_create(&c->p, b->stream, &t);
-      if (st != LBM_OK) return batch_fail(b, st, "autotune: " + g_create_error);
-      const size_t n = (size_t)G.n;
-      std::vector<double> rr(n, 0.0), rb(n, c->p.rho_b0);
-      st = lbm_init_fields(t, rr.data(), rb.data(), nullptr);
-      double best = -1.0;
       Pick p{G.nx, G.ny, G.nz, (int)c->p.storage, 32, 8};
-      for (const auto& sh : shapes) {
-        if (st != LBM_OK) break;
-        if ((st = lbm_set_tiling(t, sh[0], sh[1], 0)) != LBM_OK) break;
-        t->zchunk = 0;
-        if ((st = lbm_step(t, 1)) != LBM_OK || (st = lbm_step(t, trial_steps)) != LBM_OK) break;
-        const double ms = lbm_last_step_kernel_ms(t);
-        if (ms <= 0.0) {
-          st = LBM_EDEVICE;
-          break;
-        }
-        if (best < 0.0 || ms < best) {
-          best = ms;
-          p.tx = sh[0];
-          p.ty = sh[1];
-        }
-      }
-      const std::string terr = t->err;
-      lbm_destroy(t);
-      if (st != LBM_OK) return batch_fail(b, st, "autotune: " + terr);
+      std::string err;
+      const lbm_status st = time_tile_shapes(c, b->stream, trial_steps, p.tx, p.ty, err);
+      if (st != LBM_OK) return batch_fail(b, st, "autotune: " + err);
       picks.push_back(p);
       found = &picks.back();
     }

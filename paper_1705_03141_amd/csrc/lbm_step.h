@@ -16,7 +16,8 @@
 //      planes; barrier (the only one per plane),
 //   4. collides plane p with the gradient taken from the density ring, and stores 27
 //      deviations + 5 scalars per cell.
-// The deviations of plane p+1 stay in registers until step 4 of the next plane.
+// The deviations of plane p+1 stay in registers until step 4 of the next plane.  Steps 1-3
+// run at a raised wave priority (s_setprio), step 4 at the normal one.
 //
 // Blocks are numbered so that the blocks the hardware sends to one XCD (block ids congruent
 // modulo 8) cover consecutive tiles and z chunks: neighbouring tiles then share one L2 and
@@ -126,11 +127,6 @@ __device__ __forceinline__ float div_nc(float a, float b) {
   return a / b;
 }
 
-#ifndef LBM_PULL_GROUP
-#define LBM_PULL_GROUP 3
-#endif
-constexpr int kPullGroup = LBM_PULL_GROUP;
-
 template <typename T, int MODE, bool WANT_DF, int SX>
 __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], const float4* const (&S)[3], const float2* const (&W)[3],
                                             int idx0, const PullConst& C, float& rho, float& rho_r, float& rho_b,
@@ -177,8 +173,6 @@ __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], 
     d_rho = add_nc(d_rho, d);
     d_t = add_nc(d_t, inc);
     if constexpr (WANT_DF) df[i] = d;
-    // issue the LDS reads a few directions at a time: hoisted all at once they take ~150 VGPRs
-    if constexpr (i % kPullGroup == 0) __builtin_amdgcn_sched_barrier(0);
   });
   rho = add_nc(rho_old, d_rho);
   const float rho_t = fmaf(t_self, rho_old, d_t), rho_o = sub_nc(rho, rho_t);
@@ -342,6 +336,10 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
     const bool loads_q = !INIT && pull_q && !outlet_q;
     const int mode = plane_mode(G, zq);
 
+    // Steps 1-3 end at the workgroup's barrier, and the waves of the other workgroup on the
+    // same SIMD are usually colliding meanwhile: the pull takes the higher issue priority so
+    // that its loads go out, and the barrier is reached, sooner.
+    __builtin_amdgcn_s_setprio(1);
     // 1. scalars of plane p+3, then the populations of plane p+1
     if constexpr (!INIT) stage_load(p + 3);
     __builtin_amdgcn_sched_barrier(0);
@@ -416,6 +414,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
       const float inv = rcp(nxt.rho);
       sD[s][dI] = make_float4(nxt.rho_r * inv, nxt.rho_b * inv, nxt.rho, 0.0f);
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
 
     // 4. collide plane p

@@ -78,6 +78,8 @@ def library():
         L.lbm_init_fields.argtypes = [vp, _D, _D, _D]
         L.lbm_set_inflow.argtypes = [vp] + [ctypes.c_double] * 5 + [ctypes.c_ulonglong]
         L.lbm_set_tiling.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.lbm_autotune.argtypes = [vp, ctypes.c_int]
+        L.lbm_get_tiling.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int)] * 3
         L.lbm_step.argtypes = [vp, ctypes.c_int]
         L.lbm_sync.argtypes = [vp]
         L.lbm_step_count.argtypes = [vp]
@@ -115,7 +117,7 @@ def library():
         L.lbm_batch_destroy.restype = None
         for name in header_functions():
             getattr(L, name).restype = getattr(L, name).restype  # resolves every declared symbol
-        for name in ("lbm_create", "lbm_init_fields", "lbm_set_inflow", "lbm_set_tiling", "lbm_step", "lbm_sync",
+        for name in ("lbm_create", "lbm_init_fields", "lbm_set_inflow", "lbm_set_tiling", "lbm_autotune", "lbm_get_tiling", "lbm_step", "lbm_sync",
                      "lbm_read_field", "lbm_read_field_box", "lbm_read_populations", "lbm_save_state",
                      "lbm_load_state", "lbm_diagnostics", "lbm_selftest_collide_host", "lbm_batch_create",
                      "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_size"):
@@ -222,6 +224,17 @@ class Lattice:
             lbm_set_tiling(self.ctx, *tiling)
         if init:
             self.init_fields(problem.rho_r, problem.rho_b, problem.u)
+
+    def autotune(self, trial_steps: int = 20):
+        """Time the supported tile shapes on a scratch lattice and keep the fastest
+        (lbm_autotune)."""
+        _check(self.ctx, library().lbm_autotune(self.ctx, int(trial_steps)))
+
+    def tiling(self) -> tuple:
+        """(tx, ty, zchunk) of the step kernel (lbm_get_tiling)."""
+        v = [ctypes.c_int() for _ in range(3)]
+        _check(self.ctx, library().lbm_get_tiling(self.ctx, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def close(self):
         if getattr(self, "ctx", None):

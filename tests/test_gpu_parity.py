@@ -119,6 +119,27 @@ def test_tilings_ragged_domain(O, tiling):
     assert err < 2e-6, err
 
 
+def test_autotune_keeps_state_and_results():
+    """lbm_autotune times the tile shapes on a scratch lattice: the context's state is
+    untouched, the chosen shape is a supported one, and the steps after it agree bit for bit
+    with the default tiling."""
+    pb = W.static_droplet(dims=(70, 36, 20), radius=7.0, rho_r0=1.5, rho_b0=1.0, nu=0.05, A=0.01)
+    log("[autotune] 70x36x20")
+    lat = lbm.Lattice(pb)
+    ref_lat = lbm.Lattice(pb)
+    before = lat.populations()
+    lat.autotune(trial_steps=3)
+    assert np.array_equal(lat.populations(), before)
+    tx, ty, _ = lat.tiling()
+    assert (tx, ty) in ((32, 8), (64, 4), (32, 4))
+    lat.step(15)
+    ref_lat.step(15)
+    assert lat.tiling()[2] >= 1
+    assert np.array_equal(lat.populations(), ref_lat.populations())
+    lat.close()
+    ref_lat.close()
+
+
 def test_degenerate_lattices(O):
     """Quasi-1-D lattice (1 x 64 x 1, a shear wave) and zero steps."""
     L_ = 64
