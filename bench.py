@@ -34,8 +34,8 @@ PEAK_GBS = 8000.0
 # HBM bytes per step-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
 # scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000); valid
 # only for the kernel sources they were taken on.
-COUNTERS = {"sources_sha16": "17dd3425c15b51e0", "storage": "f32", "fetch_kib": 579288.7, "fetch_scale": 2.0,
-            "write_kib": 1048576.0, "write_scale": 1.0}
+COUNTERS = {"sources_sha16": "19551849d330d7d8", "storage": "f32", "fetch_kib": 557888.9, "fetch_scale": 2.0,
+            "write_kib": 1048576.0, "write_scale": 1.0, "tile": [64, 4]}
 KERNEL_SOURCES = ["csrc/lbm_cell.h", "csrc/lbm_device.h", "csrc/lbm_kernels.h", "csrc/lbm_kernels_impl.h",
                   "csrc/lbm_step.h", "csrc/lbm_storage_f32.hip", "build.py"]
 STD_BYTES = 432.0  # 2 colours x 27 populations x 4 B, read + write
@@ -46,7 +46,7 @@ def state_bytes(storage: str) -> float:
     return 2.0 * (27 * elem + 5 * 4)
 
 
-def run_gpu(pb, storage, steps, warmup, autotune=True):
+def run_gpu(pb, storage, steps, warmup, autotune=False):
     import torch
     from paper_1705_03141_amd import lbm
 
@@ -78,10 +78,11 @@ def kernel_sources_sha16() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str):
-    """HBM bytes per launch, or None when the counters were taken on other kernel sources."""
+def measured_traffic(storage: str, tile):
+    """HBM bytes per launch, or None when the counters were taken on other kernel sources or
+    another tile shape."""
     c = COUNTERS
-    if storage != c["storage"] or kernel_sources_sha16() != c["sources_sha16"]:
+    if storage != c["storage"] or kernel_sources_sha16() != c["sources_sha16"] or list(tile[:2]) != c["tile"]:
         return None
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
@@ -243,7 +244,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
-    ap.add_argument("--no-autotune", action="store_true", help="use the default tile shape instead of timing them")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the tile shapes first (lbm_autotune) instead of using the default 64 x 4")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--sweep", action="store_true",
@@ -277,7 +279,7 @@ def main():
     pb = W.cfg_rayleigh_taylor()
     n = pb.ncells
     log(f"{pb.name} {pb.nx}x{pb.ny}x{pb.nz}, storage {args.storage}, {args.warmup}+{args.steps} steps")
-    wall, kernel_ms, diag = run_gpu(pb, args.storage, args.steps, args.warmup, not args.no_autotune)
+    wall, kernel_ms, diag = run_gpu(pb, args.storage, args.steps, args.warmup, args.autotune)
     log(f"{wall * 1e3 / args.steps:.3f} ms/step wall, kernel {kernel_ms:.3f} ms, tiling {diag['tiling']}")
     if diag["unstable"]:
         print("bench.py: the run went unstable", file=sys.stderr)
@@ -288,7 +290,7 @@ def main():
              "state_traffic_frac": state_bytes(args.storage) * n / (kernel_ms * 1e-3) / 1e9 / PEAK_GBS}
     for st in ("f16", "bf16"):
         if st != args.storage and not args.no_extra:
-            w2, k2, _ = run_gpu(pb, st, max(args.steps // 2, 10), args.warmup, not args.no_autotune)
+            w2, k2, _ = run_gpu(pb, st, max(args.steps // 2, 10), args.warmup, args.autotune)
             log(f"storage {st}: kernel {k2:.3f} ms")
             extra[f"{st}_mlups"] = n * max(args.steps // 2, 10) / w2 / 1e6
     line = {
@@ -308,7 +310,7 @@ def main():
                    "atwood": 0.5, "g": 1e-5, "reynolds": 256, "storage": args.storage,
                    "tile": list(diag["tiling"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_GBS, "traffic": measured_traffic(args.storage)},
+                     "frac": achieved / PEAK_GBS, "traffic": measured_traffic(args.storage, diag["tiling"])},
         "extra": extra,
     }
     if not args.no_cpu_baseline:
