@@ -83,6 +83,16 @@ def test_create_without_gpu_reports_device_error(L):
     _expect(lbm.LBM_EDEVICE, W.cfg_static_droplet())
 
 
+def test_null_context_arguments_are_rejected(L):
+    """Calls on a NULL context return LBM_EINVAL without touching a device."""
+    i = ctypes.c_int()
+    assert L.lbm_autotune(None, 5) == lbm.LBM_EINVAL
+    assert L.lbm_get_tiling(None, ctypes.byref(i), ctypes.byref(i), ctypes.byref(i)) == lbm.LBM_EINVAL
+    assert L.lbm_set_tiling(None, 32, 8, 0) == lbm.LBM_EINVAL
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_sync(None) == lbm.LBM_EINVAL
+
+
 @pytest.mark.parametrize("case", ["droplet", "suga_ratio3", "force_rt"])
 def test_host_collision_matches_oracle(oracle_lib, case):
     O = oracle_lib
@@ -120,7 +130,6 @@ def test_sigma_helpers_match_table2(L):
     lbm_A_from_sigma inverts lbm_sigma_from_A."""
     import math
     import os
-    import numpy as np
     rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table2_oscillating_droplet.txt"))
     for nu, A, sigma, _ in rows:
         s = lbm.sigma_from_A(A, nu)
