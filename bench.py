@@ -257,7 +257,7 @@ def main():
                          "storage and print the interface-position error of the half-precision runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design only)", file=sys.stderr)
         sys.exit(2)
 
