@@ -1,0 +1,41 @@
+"""Host logic of bench.py (no GPU needed): the one-GPU guard and the rule that HBM traffic
+from the profiler counters is reported only for the kernel sources, storage and tile shape
+the counters were taken on."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_traffic_only_for_the_profiled_configuration(monkeypatch):
+    c = dict(bench.COUNTERS)
+    c["sources_sha16"] = bench.kernel_sources_sha16()
+    monkeypatch.setattr(bench, "COUNTERS", c)
+    t = bench.measured_traffic("f32", [64, 4, 64])
+    assert t == pytest.approx((c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0)
+    assert bench.measured_traffic("f16", [64, 4, 64]) is None
+    assert bench.measured_traffic("f32", [32, 8, 64]) is None
+    c["sources_sha16"] = "0" * 16
+    assert bench.measured_traffic("f32", [64, 4, 64]) is None
+
+
+def test_counters_are_plausible_for_the_state():
+    """The stored counters describe one FP32 step of the 128x128x512 workload: writes are the
+    128-byte state of every cell, reads at least that."""
+    c = bench.COUNTERS
+    cells = 128 * 128 * 512
+    assert c["write_kib"] * c["write_scale"] * 1024 == pytest.approx(128 * cells, rel=0.01)
+    assert c["fetch_kib"] * c["fetch_scale"] * 1024 >= 128 * cells
