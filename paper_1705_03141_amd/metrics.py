@@ -131,3 +131,67 @@ def oscillation_period(ts, values, skip: int = 1) -> float:
 def equivalent_radius(phi: np.ndarray) -> float:
     """Radius of the sphere with the volume of the cells where phi > 0 (the droplet)."""
     return float((3.0 * float((np.asarray(phi) > 0).sum()) / (4.0 * np.pi)) ** (1.0 / 3.0))
+
+
+def jet_blobs(phi: np.ndarray, inlet_plane: int = 0) -> dict:
+    """Connected regions of the jet fluid (phi > 0, 26-connected, x and y periodic) of a
+    jet lattice [z][y][x]: the column (the region that touches the inlet plane) and the
+    detached drops.  Returns the column's length (its largest z + 1), the drops' equivalent
+    diameters (6 V / pi)^(1/3) sorted in decreasing order, and the column's cross-section
+    radius sqrt(area / pi) per plane."""
+    from scipy import ndimage
+
+    mask = phi > 0.0
+    lab, n = ndimage.label(mask, structure=np.ones((3, 3, 3), dtype=bool))
+    if n == 0:
+        return {"column_length": 0.0, "drops": np.zeros(0), "radius": np.zeros(phi.shape[0])}
+    # regions that touch across the periodic x and y faces are one region
+    parent = np.arange(n + 1)
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a_face, b_face in ((lab[:, :, 0], lab[:, :, -1]), (lab[:, 0, :], lab[:, -1, :])):
+        both = (a_face > 0) & (b_face > 0)
+        for a, b in zip(a_face[both], b_face[both]):
+            ra, rb = find(a), find(b)
+            if ra != rb:
+                parent[max(ra, rb)] = min(ra, rb)
+    roots = np.array([find(k) for k in range(n + 1)])
+    lab = roots[lab]
+    sizes = np.bincount(lab.ravel(), minlength=n + 1)
+    col = set(np.unique(lab[inlet_plane][lab[inlet_plane] > 0]).tolist())
+    drops = [sizes[k] for k in np.unique(lab[lab > 0]) if k not in col]
+    colmask = np.isin(lab, list(col)) if col else np.zeros_like(mask)
+    zs = np.nonzero(colmask.any(axis=(1, 2)))[0]
+    return {"column_length": float(zs.max() + 1) if zs.size else 0.0,
+            "drops": np.sort((6.0 * np.asarray(drops, dtype=float) / np.pi) ** (1.0 / 3.0))[::-1],
+            "radius": np.sqrt(colmask.sum(axis=(1, 2)) / np.pi)}
+
+
+def jet_head_and_stem(radius: np.ndarray, column_length: float, D: float) -> tuple:
+    """Mushroom-head measure of a jet column (Sec. IV B): the largest cross-section radius
+    in the leading 40 % of the column and the radius 2 D from the inlet, both over the inlet
+    radius D/2 (nan when the column is shorter than 2 D)."""
+    L = int(column_length)
+    if L <= 2 * D:
+        return float("nan"), float("nan")
+    return float(radius[int(0.6 * L):L].max() / (D / 2)), float(radius[int(2 * D)] / (D / 2))
+
+
+def jet_axis_offset(phi: np.ndarray, column_length: float, D: float) -> float:
+    """Largest distance, over the planes of the column, between the centroid of the jet fluid
+    (phi > 0) in the plane and the inlet axis, in units of D: 0 for an axisymmetric column,
+    of order D once it winds (Sec. IV B-C)."""
+    nz, ny, nx = phi.shape
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    xc, yc = (nx - 1) / 2.0, (ny - 1) / 2.0
+    off = 0.0
+    for z in range(0, int(column_length)):
+        m = phi[z] > 0.0
+        if m.sum() >= 4:
+            off = max(off, float(np.hypot(xx[m].mean() - xc, yy[m].mean() - yc)))
+    return off / D

@@ -314,6 +314,32 @@ def regime_sweep(ncases: int = 64, seed: int = 4, sizes=(96, 112, 128, 144, 160)
     return cases
 
 
+# Lattice-unit parameters of the paper's liquid-liquid jets (Sec. IV B, Table III; Sec. IV C,
+# Table IV): inlet diameter D, inlet speed u, rho_c (rho_j = 1), sigma, nu_j, nu_c, g, and
+# the 8D x 8D x 20D lattice.
+PAPER_JETS = {
+    "ref": dict(D=25, u=0.10, rho_c=0.70, sigma=1.1e-3, nu_j=7.4e-4, nu_c=1.8e-4, g=4.7e-5),
+    "case1": dict(D=15, u=0.05, rho_c=0.70, sigma=9.1e-3, nu_j=1.6e-3, nu_c=3.9e-4, g=2.0e-5),
+    "case2": dict(D=30, u=0.10, rho_c=0.70, sigma=3.0e-5, nu_j=8.8e-4, nu_c=2.1e-4, g=3.9e-5),
+}
+
+
+def paper_jet(case: str = "ref", fields: bool = True) -> Problem:
+    """One of the paper's jets at its own size (Sec. IV B-C): "ref" (200 x 200 x 500, sinuous
+    breakup, Regime II), "case1" (120 x 120 x 300, varicose, Regime I) or "case2"
+    (240 x 240 x 600, atomisation, Regime III).  No inflow noise: the paper adds no
+    perturbation, the instability grows from the flow itself.  A is set from sigma at the
+    continuous phase's relaxation time."""
+    c = PAPER_JETS[case]
+    D, u = c["D"], c["u"]
+    pb = jet(nx=8 * D, ny=8 * D, nz=20 * D, diameter=float(D), u_in=u, gamma=1.0 / c["rho_c"], nu_c=c["nu_c"],
+             eta=c["nu_j"] / c["nu_c"], weber=u * u * D / c["sigma"], froude=u * u / (c["g"] * D), noise_rel=0.0,
+             fields=fields)
+    pb.name = f"paper_jet_{case}_{8 * D}x{8 * D}x{20 * D}"
+    pb.t_unit = D / u  # steps per unit of t* = t u / D
+    return pb
+
+
 UNIT_RATES = (0.0,) * 4 + (1.0,) * 23
 
 

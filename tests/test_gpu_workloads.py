@@ -1,7 +1,8 @@
 """The paper's test problems run on the GPU with their measurements (Secs. III, IV, V): the
 Laplace law of the static droplet at the paper's size and length against its table of
 errors, interface tracking of the oscillating droplet against the oracle, Rayleigh-Taylor
-front positions, the jet's leading edge at full size, and the stable ranges of density and
+front positions, the jet's leading edge at full size, the paper's three jets at their own
+sizes against its description of their breakup regimes, and the stable ranges of density and
 viscosity ratio the paper states."""
 import math
 import os
@@ -74,6 +75,74 @@ def test_jet_leading_edge_advances():
     log(f"[jet] leading edge after 2000 steps: z = {z:.1f} (plug travel {travel:.1f}); unstable {d['unstable']}")
     assert not d["unstable"]
     assert 0.3 * travel < z < 1.2 * travel
+
+
+def _run_paper_jet(case, tstars):
+    """Advance one of the paper's jets (no inflow noise) to each t* in turn and measure its
+    column and drops there."""
+    pb = W.paper_jet(case)
+    D = pb.diameter
+    lat = lbm.Lattice(pb)
+    out, done = {}, 0
+    for ts in tstars:
+        n = int(round(ts * pb.t_unit)) - done
+        lat.step(n)
+        done += n
+        d = lat.diagnostics()
+        assert not d["unstable"], (case, ts)
+        phi = lat.field("phi")
+        b = metrics.jet_blobs(phi)
+        head, stem = metrics.jet_head_and_stem(b["radius"], b["column_length"], D)
+        r = {"L": b["column_length"] / D, "drops": b["drops"] / D, "head": head, "stem": stem,
+             "offset": metrics.jet_axis_offset(phi, b["column_length"], D)}
+        log(f"[{pb.name}] t*={ts}: column {r['L']:.2f} D, {len(r['drops'])} drops "
+            f"(largest {r['drops'].max() if len(r['drops']) else 0:.2f} D), head {head:.2f}, stem {stem:.2f}, "
+            f"axis offset {r['offset']:.3f} D")
+        out[ts] = r
+    lat.close()
+    return out
+
+
+def test_paper_jet_case1_varicose():
+    """Case 1 of Sec. IV C (120 x 120 x 300, Re = 4.6e2, We = 4.1, Regime I): no mushroom
+    head, the column stays axisymmetric, and at t* = 30 its tip has pinched off into one
+    drop at least as large as the inlet diameter, with no satellite drops (the paper's
+    description of its varicose-breakup figure)."""
+    r = _run_paper_jet("case1", [17, 22, 30, 40])
+    assert len(r[17]["drops"]) == 0 and len(r[22]["drops"]) == 0
+    assert r[22]["head"] < 1.5 * r[22]["stem"]          # a swollen column, no distinct head
+    for ts in (30, 40):
+        drops = r[ts]["drops"]
+        assert 1 <= len(drops) <= 2, (ts, drops)
+        assert drops.max() >= 1.0 and drops.min() >= 0.3, (ts, drops)
+    assert max(x["offset"] for x in r.values()) < 0.05
+
+
+def test_paper_jet_reference_sinuous():
+    """Reference jet of Sec. IV B (200 x 200 x 500, gamma = 1.4, eta = 4.2, Re = 3.4e3,
+    We = 2.2e2, Fr = 8.5) to t* = 72: it stays stable at this viscosity ratio; a mushroom
+    head wider than the stem leads the column; later drops are entrained from its side and
+    the column winds off the axis (Regime IIb)."""
+    r = _run_paper_jet("ref", [9, 15, 72])
+    for ts in (9, 15):
+        assert r[ts]["head"] > 1.5 * r[ts]["stem"], ts
+        assert r[ts]["offset"] < 0.05
+    drops = r[72]["drops"]
+    assert 10 <= len(drops) <= 150, len(drops)
+    assert np.median(drops) < 0.5
+    assert r[72]["offset"] > 0.25
+
+
+def test_paper_jet_case2_atomisation():
+    """Case 2 of Sec. IV C (240 x 240 x 600, Re = 3.4e3, We = 1.0e4, Regime III): a mushroom
+    head at t* = 8, then active entrainment: by t* = 33 the drops number in the hundreds
+    (against one in Case 1 and tens in the reference jet) and are much smaller than the
+    inlet diameter."""
+    r = _run_paper_jet("case2", [8, 33])
+    assert r[8]["head"] > 1.3 * r[8]["stem"]
+    drops = r[33]["drops"]
+    assert len(drops) >= 150, len(drops)
+    assert np.median(drops) < 0.3
 
 
 def _laplace_table():

@@ -410,6 +410,43 @@ def test_jet_dimensionless_groups():
     assert W.breakup_regime(3.4e3, 3.0e-2) == "III"
 
 
+def test_paper_jet_problems_follow_the_golden_parameters():
+    """workloads.paper_jet builds each jet of Secs. IV B-C on its 8D x 8D x 20D lattice with
+    the lattice-unit values of the golden table: rho_c, nu_j, nu_c, g, D, u, and A giving
+    the listed sigma at the continuous phase (Eq. (sigma)); no inflow noise."""
+    with open(golden_path("jet_parameters.txt")) as fh:
+        lines = [l for l in fh if l.strip() and not l.startswith("#")]
+    for line in lines:
+        name, D, u, rc, sigma, nuj, nuc, g = line.split("|")[0].split()
+        pb = W.paper_jet(name, fields=False)
+        D = float(D)
+        assert (pb.nx, pb.ny, pb.nz) == (8 * D, 8 * D, 20 * D) and pb.diameter == D
+        assert pb.u_in == float(u) and pb.noise_rel == 0.0 and pb.t_unit == D / float(u)
+        for got, want in ((pb.rho_b0, float(rc)), (pb.nu_r, float(nuj)), (pb.nu_b, float(nuc)), (pb.g[2], float(g)),
+                          (4 / 9 * pb.A * (3 * pb.nu_b + 0.5), float(sigma))):
+            assert abs(got - want) <= 1e-12 * want, (name, got, want)
+        assert pb.rho_r0 == 1.0
+
+
+def test_jet_blob_measurement():
+    """metrics.jet_blobs on a hand-made field: the column touching the inlet plane, one drop
+    that wraps across the periodic x face (one region, 40 cells) and a one-cell drop."""
+    from paper_1705_03141_amd import metrics
+    phi = -np.ones((40, 20, 20))
+    phi[0:10, 8:12, 8:12] = 1.0
+    phi[20:24, 0:2, 0:3] = 1.0
+    phi[20:24, 0:2, 18:20] = 1.0
+    phi[30, 5, 5] = 1.0
+    b = metrics.jet_blobs(phi)
+    assert b["column_length"] == 10.0
+    want = np.array([(6 * 40 / np.pi) ** (1 / 3), (6 / np.pi) ** (1 / 3)])
+    assert np.allclose(b["drops"], want)
+    assert np.allclose(b["radius"][:10], np.sqrt(16 / np.pi)) and not b["radius"][10:].any()
+    head, stem = metrics.jet_head_and_stem(b["radius"], b["column_length"], 2.0)
+    assert head == stem == np.sqrt(16 / np.pi) / 1.0
+    assert metrics.jet_axis_offset(phi, b["column_length"], 2.0) == 0.0
+
+
 def test_splitmix64_known_answers(O):
     """SplitMix64 with state 0 produces 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
     0x06C45D188009454F (reference implementation of Steele, Lea & Flood)."""
