@@ -195,3 +195,10 @@ def jet_axis_offset(phi: np.ndarray, column_length: float, D: float) -> float:
         if m.sum() >= 4:
             off = max(off, float(np.hypot(xx[m].mean() - xc, yy[m].mean() - yc)))
     return off / D
+
+
+def interface_area(phi: np.ndarray) -> int:
+    """Number of cell faces across which phi changes sign: a measure of the interface area
+    (in lattice units squared, staircase-counted) that grows as the interface folds."""
+    m = phi > 0.0
+    return int((m[1:] != m[:-1]).sum() + (m[:, 1:] != m[:, :-1]).sum() + (m[:, :, 1:] != m[:, :, :-1]).sum())

@@ -314,6 +314,18 @@ def regime_sweep(ncases: int = 64, seed: int = 4, sizes=(96, 112, 128, 144, 160)
     return cases
 
 
+def paper_rayleigh_taylor(reynolds: float) -> Problem:
+    """The Rayleigh-Taylor runs of Sec. III C at the paper's size: 128 x 128 x 512,
+    At = 0.5, (W g)^(1/2) = 0.04, no interfacial tension, equal viscosities from Re, the
+    single-mode perturbation and no noise.  t* = t / (W/g)^(1/2), 3200 steps per unit."""
+    W = 128
+    g = 0.04 ** 2 / W
+    pb = rayleigh_taylor(width=W, atwood=0.5, g=g, reynolds=float(reynolds), noise=0.0)
+    pb.name = f"paper_rayleigh_taylor_Re{reynolds:g}"
+    pb.t_unit = math.sqrt(W / g)
+    return pb
+
+
 # Lattice-unit parameters of the paper's liquid-liquid jets (Sec. IV B, Table III; Sec. IV C,
 # Table IV): inlet diameter D, inlet speed u, rho_c (rho_j = 1), sigma, nu_j, nu_c, g, and
 # the 8D x 8D x 20D lattice.

@@ -77,6 +77,45 @@ def test_jet_leading_edge_advances():
     assert 0.3 * travel < z < 1.2 * travel
 
 
+def test_paper_rayleigh_taylor_reynolds_dependence():
+    """The Rayleigh-Taylor runs of Sec. III C (128 x 128 x 512, At = 0.5, Re = 512, 1024 and
+    5120) to t* = 4: all stay stable; the spike tip, bubble front and saddle point move
+    almost independently of Re (the paper's finding for Re > 512, after He et al.); and the
+    interface folds more at higher Re in the later stages while it hardly differs early on."""
+    width = 128
+    runs = {}
+    for Re in (512, 1024, 5120):
+        pb = W.paper_rayleigh_taylor(Re)
+        zm = (pb.nz - 1) / 2.0
+        lat = lbm.Lattice(pb)
+        out, done = {}, 0
+        for ts in (1, 2, 3, 4):
+            n = int(round(ts * pb.t_unit)) - done
+            lat.step(n)
+            done += n
+            assert not lat.diagnostics()["unstable"], (Re, ts)
+            phi = lat.field("phi")
+            f = metrics.rt_front_positions(phi)
+            out[ts] = {k: (v - zm) / width for k, v in f.items()}
+            out[ts]["area"] = metrics.interface_area(phi)
+            log(f"[RT Re={Re}] t*={ts}: spike {out[ts]['spike']:+.3f} W, bubble {out[ts]['bubble']:+.3f} W, "
+                f"saddle {out[ts]['saddle']:+.3f} W, interface {out[ts]['area']}")
+        lat.close()
+        runs[Re] = out
+    for ts in (1, 2, 3, 4):
+        for key in ("spike", "bubble") + (("saddle",) if ts <= 3 else ()):
+            vals = [runs[Re][ts][key] for Re in runs]
+            assert max(vals) - min(vals) < 0.1, (ts, key, vals)
+    for Re in runs:
+        sp = [runs[Re][ts]["spike"] for ts in (1, 2, 3, 4)]
+        bu = [runs[Re][ts]["bubble"] for ts in (1, 2, 3, 4)]
+        assert all(b > a for a, b in zip(sp, sp[1:])) and all(b < a for a, b in zip(bu, bu[1:]))
+    early = [runs[Re][1]["area"] for Re in (512, 1024, 5120)]
+    late = [runs[Re][4]["area"] for Re in (512, 1024, 5120)]
+    assert late[0] < late[1] < late[2] and late[2] > 1.4 * late[0]
+    assert early[2] < 1.1 * early[0]
+
+
 def _run_paper_jet(case, tstars):
     """Advance one of the paper's jets (no inflow noise) to each t* in turn and measure its
     column and drops there."""

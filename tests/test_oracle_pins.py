@@ -428,6 +428,28 @@ def test_paper_jet_problems_follow_the_golden_parameters():
         assert pb.rho_r0 == 1.0
 
 
+def test_paper_rayleigh_taylor_problem():
+    """workloads.paper_rayleigh_taylor follows Sec. III C: 128 x 128 x 512, At = 0.5,
+    (W g)^(1/2) = 0.04, Re = (W g)^(1/2) W / nu, no interfacial tension, no noise."""
+    for Re in (512, 1024, 5120):
+        pb = W.paper_rayleigh_taylor(Re)
+        assert (pb.nx, pb.ny, pb.nz) == (128, 128, 512) and pb.A == 0.0
+        assert abs((pb.rho_r0 - pb.rho_b0) / (pb.rho_r0 + pb.rho_b0) - 0.5) < 1e-15
+        assert abs((128 * pb.g[2]) ** 0.5 - 0.04) < 1e-15
+        assert abs(0.04 * 128 / pb.nu_r - Re) < 1e-9 * Re and pb.nu_b == pb.nu_r
+        assert abs(pb.t_unit - (128 / pb.g[2]) ** 0.5) < 1e-9
+
+
+def test_interface_area_counts_faces():
+    from paper_1705_03141_amd import metrics
+    phi = -np.ones((6, 5, 4))
+    assert metrics.interface_area(phi) == 0
+    phi[3:] = 1.0                     # a flat interface: one face per column
+    assert metrics.interface_area(phi) == 5 * 4
+    phi[0, 0, 0] = 1.0                # an isolated cell adds its three inner faces
+    assert metrics.interface_area(phi) == 5 * 4 + 3
+
+
 def test_jet_blob_measurement():
     """metrics.jet_blobs on a hand-made field: the column touching the inlet plane, one drop
     that wraps across the periodic x face (one region, 40 cells) and a one-cell drop."""
