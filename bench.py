@@ -201,8 +201,9 @@ def interface_error(workload: str, steps: int):
     """Interface-position error of FP16 / BF16 storage against FP32 storage after `steps`
     steps (metrics.interface_position_error; lattice units).  The control "f32_perturbed" is
     an FP32 run whose initial red density differs by a relative 1e-6 (eight FP32 units in the
-    last place) in one cell on the seeded interface: what the flow itself makes of a
-    rounding-sized difference, the floor any storage format is measured against."""
+    last place) in one cell on the seeded interface (for the jet, which starts without red
+    fluid, the blue density of the axis cell above the inlet): what the flow itself makes of
+    a rounding-sized difference, the floor any storage format is measured against."""
     import copy
 
     import numpy as np
@@ -211,11 +212,16 @@ def interface_error(workload: str, steps: int):
 
     pb = W.cfg_rayleigh_taylor() if workload == "rt" else W.cfg_jet()
     ctrl = copy.copy(pb)
-    ctrl.rho_r = pb.rho_r.copy()
-    # the cell of the column through the middle where the red fraction is nearest 1/2
     k = pb.nx // 2
-    col = pb.rho_r[:, k, k] / (pb.rho_r[:, k, k] + pb.rho_b[:, k, k])
-    ctrl.rho_r[int(np.argmin(np.abs(col - 0.5))), k, k] *= 1.0 + 1e-6
+    if pb.rho_r.any():
+        # the cell of the column through the middle where the red fraction is nearest 1/2
+        ctrl.rho_r = pb.rho_r.copy()
+        col = pb.rho_r[:, k, k] / (pb.rho_r[:, k, k] + pb.rho_b[:, k, k])
+        ctrl.rho_r[int(np.argmin(np.abs(col - 0.5))), k, k] *= 1.0 + 1e-6
+    else:
+        # no red fluid at t = 0 (the jet): the blue cell on the axis one plane above the inlet
+        ctrl.rho_b = pb.rho_b.copy()
+        ctrl.rho_b[1, k, k] *= 1.0 + 1e-6
     phi = {}
     for st, prob in (("f32", pb), ("f32_perturbed", ctrl), ("f16", pb), ("bf16", pb)):
         lat = lbm.Lattice(prob, storage=st.split("_")[0])
