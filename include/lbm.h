@@ -98,11 +98,11 @@ lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho_r, const double *rho_
 lbm_status lbm_set_inflow(lbm_ctx *ctx, double xc, double yc, double diameter, double u_normal, double noise_rel,
                           unsigned long long seed);
 
-/* Tile shape of the step kernel: (tx, ty) in {(32, 4), (32, 8), (32, 16), (64, 4), (64, 8)} cells per workgroup,
- * zchunk >= 1 z planes per workgroup, or 0 to let the library choose it from the number of
- * workgroups the device holds at once.  Default: (64, 4, 0) for nx >= 64, (32, 8, 0)
- * otherwise.  Results do not depend on the
- * tiling; this is a tuning hook.  LBM_EINVAL for other shapes or zchunk < 0. */
+/* Tile shape of the step kernel: (tx, ty) in {(32, 4), (32, 8), (32, 16), (64, 4), (64, 8)}
+ * cells per workgroup, zchunk >= 1 z planes per workgroup, or 0 to let the library choose
+ * it from the number of workgroups the device holds at once.  Default: (64, 4, 0) for
+ * nx >= 64, (32, 8, 0) otherwise.  Results do not depend on the tiling; this is a tuning
+ * hook.  LBM_EINVAL for other shapes or zchunk < 0. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int tx, int ty, int zchunk);
 
 /* Time each supported tile shape (32x8, 64x4, 32x4) for trial_steps steps on a scratch
