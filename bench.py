@@ -162,6 +162,43 @@ def sweep(steps: int, warmup: int, storage: str = "f16"):
     b.close()
 
 
+def slab_bench(steps: int, warmup: int):
+    """One GPU's share of the jet 256 x 256 x 1024 split into z-slabs over 8 GPUs: the step
+    kernel on a 256 x 256 x 128 slab of jet physics (gamma 1.6, nu 1.8e-4, We 220, a red
+    column of D = 16 through it), z periodic in place of the two neighbouring slabs.  Reports
+    the step time, and the bytes of the two boundary planes of the 32-value state a slab
+    would send per step: they are contiguous in the [z][value][y][x] layout, so they go to
+    RCCL without packing."""
+    import numpy as np
+    from paper_1705_03141_amd import workloads as W
+
+    pb = W.jet(nx=256, ny=256, nz=128, diameter=16.0, u_in=0.04, gamma=1.6, nu_c=1.8e-4, eta=1.0, weber=220.0,
+               froude=8.5, noise_rel=0.0, fields=False)
+    pb.faces = (W.PERIODIC,) * 6
+    pb.inflow = False
+    pb.name = "jet_slab_256x256x128"
+    y, x = np.mgrid[0:pb.ny, 0:pb.nx]
+    inside = ((x - 127.5) ** 2 + (y - 127.5) ** 2 < 64.0)[None].repeat(pb.nz, axis=0)
+    pb.rho_r = np.where(inside, pb.rho_r0, 0.0)
+    pb.rho_b = np.where(inside, 0.0, pb.rho_b0)
+    pb.u = np.zeros((3, pb.nz, pb.ny, pb.nx))
+    pb.u[2][inside] = 0.04
+    n = pb.ncells
+    wall, kernel_ms, diag = run_gpu(pb, "f32", steps, warmup)
+    if diag["unstable"]:
+        print("bench.py: the slab went unstable", file=sys.stderr)
+        sys.exit(1)
+    face_bytes = 2 * (27 + 5) * 4 * pb.nx * pb.ny
+    line = {"metric": "MLUPS, one z-slab of the jet (8-GPU share)", "value": n * steps / wall / 1e6, "unit": "MLUPS",
+            "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3 / steps, "kernel_ms": kernel_ms,
+            "dtype": "f32", "config": {"workload": pb.name, "tile": list(diag["tiling"])},
+            "roofline": {"bound": "hbm", "achieved": STD_BYTES * n / (kernel_ms * 1e-3) / 1e9, "peak": PEAK_GBS,
+                         "unit": "GB/s", "frac": STD_BYTES * n / (kernel_ms * 1e-3) / 1e9 / PEAK_GBS},
+            "halo_bytes_per_step": face_bytes,
+            "halo_us_at_153GBps_per_link": face_bytes / 2 / 153e9 * 1e6}
+    print(json.dumps(line), flush=True)
+
+
 def surrogate_bench(steps: int, warmup: int):
     """Training steps (forward, backward, Adam) of the surrogate on one 64 x 64 x 256 coarse
     state; throughput of its convolutions against the dense BF16 MFMA peak (2.5 PFLOP/s)."""
@@ -256,6 +293,8 @@ def main():
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--sweep", action="store_true",
                     help="instead: time the 64-case regime-map sweep of uneven jets in one batch (FP16 storage)")
+    ap.add_argument("--slab", action="store_true",
+                    help="instead: time one GPU's z-slab (256 x 256 x 128) of the jet split over 8 GPUs")
     ap.add_argument("--surrogate", action="store_true",
                     help="instead: time training steps of the surrogate network on the 64 x 64 x 256 x 4 input")
     ap.add_argument("--interface-error", choices=["rt", "jet"],
@@ -278,6 +317,9 @@ def main():
         return
     if args.surrogate:
         surrogate_bench(args.steps, args.warmup)
+        return
+    if args.slab:
+        slab_bench(args.steps, args.warmup)
         return
 
     from paper_1705_03141_amd import workloads as W
