@@ -35,7 +35,8 @@ PEAK_GBS = 8000.0
 # scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000); valid
 # only for the kernel sources they were taken on.
 COUNTERS = {"sources_sha16": "19551849d330d7d8", "storage": "f32", "fetch_kib": 557888.9, "fetch_scale": 2.0,
-            "write_kib": 1048576.0, "write_scale": 1.0, "tile": [64, 4]}
+            "write_kib": 1048576.0, "write_scale": 1.0, "tile": [64, 4],
+            "workload": "rayleigh_taylor_128x128x512"}
 KERNEL_SOURCES = ["csrc/lbm_cell.h", "csrc/lbm_device.h", "csrc/lbm_kernels.h", "csrc/lbm_kernels_impl.h",
                   "csrc/lbm_step.h", "csrc/lbm_storage_f32.hip", "build.py"]
 STD_BYTES = 432.0  # 2 colours x 27 populations x 4 B, read + write
@@ -78,11 +79,12 @@ def kernel_sources_sha16() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str, tile):
-    """HBM bytes per launch, or None when the counters were taken on other kernel sources or
-    another tile shape."""
+def measured_traffic(storage: str, tile, workload: str = "rayleigh_taylor_128x128x512"):
+    """HBM bytes per launch, or None when the counters were taken on other kernel sources,
+    another tile shape or another workload."""
     c = COUNTERS
-    if storage != c["storage"] or kernel_sources_sha16() != c["sources_sha16"] or list(tile[:2]) != c["tile"]:
+    if (storage != c["storage"] or kernel_sources_sha16() != c["sources_sha16"] or list(tile[:2]) != c["tile"]
+            or workload != c["workload"]):
         return None
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
@@ -286,6 +288,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--workload", default="rt", choices=["rt", "jet"],
+                    help="rt: Rayleigh-Taylor 128 x 128 x 512 (the default); jet: 256 x 256 x 1024")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first (lbm_autotune) instead of using the default 64 x 4")
@@ -324,7 +328,7 @@ def main():
 
     from paper_1705_03141_amd import workloads as W
 
-    pb = W.cfg_rayleigh_taylor()
+    pb = W.cfg_rayleigh_taylor() if args.workload == "rt" else W.cfg_jet()
     n = pb.ncells
     log(f"{pb.name} {pb.nx}x{pb.ny}x{pb.nz}, storage {args.storage}, {args.warmup}+{args.steps} steps")
     wall, kernel_ms, diag = run_gpu(pb, args.storage, args.steps, args.warmup, args.autotune)
@@ -341,7 +345,7 @@ def main():
             w2, k2, _ = run_gpu(pb, st, max(args.steps // 2, 10), args.warmup, args.autotune)
             log(f"storage {st}: kernel {k2:.3f} ms")
             extra[f"{st}_mlups"] = n * max(args.steps // 2, 10) / w2 / 1e6
-    traffic = measured_traffic(args.storage, diag["tiling"])
+    traffic = measured_traffic(args.storage, diag["tiling"], pb.name)
     if traffic is not None:  # HBM bytes the counters saw, over the same kernel time
         extra["measured_hbm_gbs"] = traffic / (kernel_ms * 1e-3) / 1e9
         extra["measured_hbm_frac"] = extra["measured_hbm_gbs"] / PEAK_GBS
@@ -358,8 +362,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.storage == "f32" else f"f32 compute, {args.storage} storage",
         "data": "synthetic",
-        "config": {"workload": "rayleigh_taylor_128x128x512", "nx": pb.nx, "ny": pb.ny, "nz": pb.nz,
-                   "atwood": 0.5, "g": 1e-5, "reynolds": 256, "storage": args.storage,
+        "config": {"workload": pb.name, "nx": pb.nx, "ny": pb.ny, "nz": pb.nz, "storage": args.storage,
                    "tile": list(diag["tiling"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_GBS, "traffic": traffic},

@@ -28,6 +28,7 @@ def test_traffic_only_for_the_profiled_configuration(monkeypatch):
     assert t == pytest.approx((c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0)
     assert bench.measured_traffic("f16", [64, 4, 64]) is None
     assert bench.measured_traffic("f32", [32, 8, 64]) is None
+    assert bench.measured_traffic("f32", [64, 4, 64], "jet_256x256x1024") is None
     c["sources_sha16"] = "0" * 16
     assert bench.measured_traffic("f32", [64, 4, 64]) is None
 
