@@ -53,7 +53,8 @@ typedef enum {
 } lbm_face;
 
 typedef struct {
-  int nx, ny, nz;        /* lattice size, each >= 1; nz >= 3 when a z face is not periodic */
+  int nx, ny, nz;        /* lattice size, each >= 1; nz >= 3 when a z face is not periodic;
+                            nx*ny*108 < 2^31 (at most 19 884 107 cells per x-y plane) */
   double rho_r0, rho_b0; /* reference densities of the red and blue fluids; their ratio
                             gamma = rho_r0/rho_b0 sets alpha_r = 1 - (1 - 8/27)/gamma (Sec. II),
                             which must lie in [0, 1) */

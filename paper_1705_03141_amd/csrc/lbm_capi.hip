@@ -70,7 +70,9 @@ static const double kAlphaB = 8.0 / 27.0;
 static lbm_status check_params(const lbm_params* p, lbm_ctx* c, std::string& msg) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return msg = "lattice sizes must be >= 1", LBM_EINVAL;
   const long long plane = (long long)p->nx * p->ny;
-  if (plane * Q >= (1LL << 31)) return msg = "nx*ny too large for 32-bit plane offsets", LBM_EINVAL;
+  // the kernels address the 27 population planes of one z (4-byte words at most) with 32-bit
+  // signed byte offsets
+  if (plane * Q * 4 >= (1LL << 31)) return msg = "nx*ny too large: nx*ny*108 must stay below 2^31", LBM_EINVAL;
   if (!(p->rho_r0 > 0.0) || !(p->rho_b0 > 0.0)) return msg = "rho_r0 and rho_b0 must be > 0", LBM_EINVAL;
   const double alpha_r = 1.0 - (1.0 - kAlphaB) * p->rho_b0 / p->rho_r0;
   if (!(alpha_r >= 0.0 && alpha_r < 1.0))

@@ -50,6 +50,9 @@ def test_parameter_validation(L):
     _expect(lbm.LBM_EINVAL, pb, beta=1.5)
     _expect(lbm.LBM_EINVAL, pb, A=-1.0)
     _expect(lbm.LBM_EINVAL, pb, nx=0)
+    # the largest x-y plane the kernels' 32-bit byte offsets address: nx*ny*108 < 2^31
+    _expect(lbm.LBM_EINVAL, pb, nx=4460, ny=4460, nz=3)
+    _expect(lbm.LBM_EINVAL, pb, nx=19884108, ny=1, nz=3)
     # gamma < 19/27 gives alpha_r < 0
     _expect(lbm.LBM_EINVAL, pb, rho_r0=0.5, rho_b0=1.0)
     # x faces must be periodic; z faces paired
@@ -81,6 +84,8 @@ def test_create_without_gpu_reports_device_error(L):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     _expect(lbm.LBM_EDEVICE, W.cfg_static_droplet())
+    # the largest plane passes validation (and only then meets the missing device)
+    _expect(lbm.LBM_EDEVICE, W.cfg_static_droplet(), nx=19884107, ny=1, nz=3)
 
 
 def test_null_context_arguments_are_rejected(L):
