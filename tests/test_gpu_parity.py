@@ -96,6 +96,34 @@ def test_parity_fields(O, name, steps):
         assert e["u"] < U_TOL.get(name, TOL), e
 
 
+# ------------------------------------------------------------------ half-precision storage
+
+# FP16 / BF16 store each population's deviation g_i from rho phi_i(alpha) rounded to an
+# 11-bit / 8-bit significand, unit roundoff u = 2^-11 / 2^-8 per store, and the arithmetic
+# stays FP32.  The deviations are at most ~0.1 rho, so a step's stores move a cell's total
+# density by far less than u rho: its bar is u/2 (relative to max rho).  A colour's density
+# also moves with the interface, which the rounding displaces slightly: 2 u.  The velocity
+# bar is 50 u relative to max|u| (the droplet's velocities are spurious currents of ~1e-4,
+# so its relative velocity error is the largest).
+HALF_U = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+HALF_TOL = {k: {"rho": 0.5 * u, "colour": 2.0 * u, "u": 50.0 * u} for k, u in HALF_U.items()}
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("name", ["droplet32", "rt_small", "jet_small"])
+def test_half_storage_parity(O, name, storage):
+    """FP16 and BF16 storage against the FP64 oracle over 300 steps, within bars set by the
+    format's unit roundoff (HALF_TOL)."""
+    pb = W.small_configs()[name]
+    log(f"[half parity] {name} {storage}")
+    for s, got, ref in run_pair(pb, (100, 300), storage=storage, oracle_lib=O):
+        e = errors(got, ref)
+        log(f"  step {s}: " + " ".join(f"{k}={v:.3e}" for k, v in e.items()))
+        tol = HALF_TOL[storage]
+        assert e["rho"] < tol["rho"] and e["rho_r"] < tol["colour"] and e["rho_b"] < tol["colour"], e
+        assert e["u"] < tol["u"], e
+
+
 # ------------------------------------------------------------------ tilings, ragged sizes, edge cases
 
 @pytest.mark.parametrize("tiling", [(32, 4, 5), (32, 8, 3), (64, 4, 7), (32, 4, 64)])
