@@ -93,7 +93,7 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pb_full, steps=30):
+def cpu_baseline(pb_full, steps=150):
     import numpy as np  # noqa: F401
     import oracle
 
