@@ -45,6 +45,7 @@ class _Params(ctypes.Structure):
         ("seed", ctypes.c_ulonglong),
         ("gnx", ctypes.c_int), ("gny", ctypes.c_int), ("gnz", ctypes.c_int),
         ("ox", ctypes.c_int), ("oy", ctypes.c_int), ("oz", ctypes.c_int),
+        ("gphi_cut", ctypes.c_double),
     ]
 
 
@@ -77,8 +78,8 @@ def lib():
         L.oracle_equilibrium.argtypes = [ctypes.c_double] * 4 + [_D, ctypes.c_double, _D, _D]
         L.oracle_colour_equilibrium.argtypes = [ctypes.c_double, ctypes.c_double, _D, _D]
         L.oracle_forcing_velocity_space.argtypes = [_D, _D, _D]
-        L.oracle_perturbation.argtypes = [ctypes.c_double, _D, _D]
-        L.oracle_recolour.argtypes = [ctypes.c_double] * 4 + [_D, _D, _D, _D]
+        L.oracle_perturbation.argtypes = [ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_recolour.argtypes = [ctypes.c_double] * 5 + [_D, _D, _D, _D]
         L.oracle_collide_cell.argtypes = [ctypes.c_void_p, _D, _D, _D, _D, _D, _D, _D]
         L.oracle_gradient.argtypes = [ctypes.c_void_p, _D, _D]
         L.oracle_noise.argtypes = [ctypes.c_ulonglong, ctypes.c_ulonglong]
@@ -99,7 +100,9 @@ def _vec(x, n=None):
     return a
 
 
-def params_from_problem(pb) -> _Params:
+def params_from_problem(pb, gphi_cut: float = 0.0) -> _Params:
+    """Oracle parameters of a problem.  ``gphi_cut`` is the |grad phi| at and below which
+    the interface normal is taken as undefined (reading R7: 0, only where grad phi = 0)."""
     p = _Params()
     p.nx, p.ny, p.nz = pb.nx, pb.ny, pb.nz
     p.rho_r0, p.rho_b0, p.nu_r, p.nu_b = pb.rho_r0, pb.rho_b0, pb.nu_r, pb.nu_b
@@ -118,15 +121,16 @@ def params_from_problem(pb) -> _Params:
     p.seed = int(pb.seed)
     p.gnx, p.gny, p.gnz = pb.global_dims
     p.ox, p.oy, p.oz = pb.origin
+    p.gphi_cut = float(gphi_cut)
     return p
 
 
 class Oracle:
     """A running FP64 simulation of a :class:`workloads.Problem`."""
 
-    def __init__(self, problem, init: bool = True):
+    def __init__(self, problem, init: bool = True, gphi_cut: float = 0.0):
         self.pb = problem
-        self._p = params_from_problem(problem)
+        self._p = params_from_problem(problem, gphi_cut)
         h = ctypes.c_void_p()
         rc = lib().oracle_create(ctypes.byref(self._p), ctypes.byref(h))
         if rc != 0:
@@ -241,18 +245,18 @@ def forcing_velocity_space(u, F) -> np.ndarray:
     return out
 
 
-def perturbation(A, grad_phi, f) -> np.ndarray:
+def perturbation(A, grad_phi, f, gphi_cut: float = 0.0) -> np.ndarray:
     out = _vec(f, Q).copy()
     gp = _vec(grad_phi, 3)
-    lib().oracle_perturbation(float(A), _ptr(gp), _ptr(out))
+    lib().oracle_perturbation(float(A), float(gphi_cut), _ptr(gp), _ptr(out))
     return out
 
 
-def recolour(rho_r, rho_b, beta, alpha_bar, grad_phi, f):
+def recolour(rho_r, rho_b, beta, alpha_bar, grad_phi, f, gphi_cut: float = 0.0):
     fr, fb = np.empty(Q), np.empty(Q)
     gp, ff = _vec(grad_phi, 3), _vec(f, Q)
-    lib().oracle_recolour(float(rho_r), float(rho_b), float(beta), float(alpha_bar), _ptr(gp), _ptr(ff), _ptr(fr),
-                          _ptr(fb))
+    lib().oracle_recolour(float(rho_r), float(rho_b), float(beta), float(alpha_bar), float(gphi_cut), _ptr(gp),
+                          _ptr(ff), _ptr(fr), _ptr(fb))
     return fr, fb
 
 

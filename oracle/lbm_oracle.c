@@ -23,10 +23,11 @@
  *   R5  the perturbation operator carries the square (c_i . grad phi)^2 / |grad phi|^2,
  *       without which it does not conserve mass.
  *   R6  A is a run constant, A_r = A_b = A.
- *   R7  cos(theta_1) = 0 for the rest velocity.  Where |grad phi| < 1e-5 the direction of
- *       grad phi is not defined by the fields (at a symmetry point it is set by rounding
- *       alone) and the recolouring term beta rho_r rho_b / rho^2 cos(theta_i) does not vanish
- *       with |grad phi|; there both that term and the perturbation are taken as zero.
+ *   R7  cos(theta_1) = 0 for the rest velocity.  Both the perturbation and the recolouring
+ *       segregation need the interface normal grad phi / |grad phi|, which exists wherever
+ *       grad phi != 0; where grad phi = 0 exactly both are taken as zero (the perturbation is
+ *       continuous there; the segregation term is 0/0).  A cut-off |grad phi| <= gphi_cut
+ *       can be set for the convergence check of this reading; it is 0 by default.
  *   R8  no-slip walls are half-way bounce-back, per colour; walls lie half a cell outside
  *       the first/last plane.  Gradient stencils see a ghost layer equal to the adjacent
  *       cell (zero normal gradient).
@@ -50,7 +51,6 @@
 #include <string.h>
 
 #define Q 27
-#define GRAD_PHI_MIN 1e-5 /* R7: |grad phi| below this defines no interface normal */
 
 enum { FACE_PERIODIC = 0, FACE_BOUNCEBACK = 1, FACE_FREESLIP = 2, FACE_OUTFLOW = 3 };
 
@@ -81,6 +81,7 @@ typedef struct {
   unsigned long long seed;
   int gnx, gny, gnz;     /* dimensions of the whole domain the noise counter refers to */
   int ox, oy, oz;        /* origin of this lattice inside that domain */
+  double gphi_cut;       /* R7: no normal where |grad phi| <= gphi_cut (0: only grad phi = 0) */
 } oracle_params;
 
 typedef struct {
@@ -282,9 +283,9 @@ static void mrt_collide(const double M[Q][Q], const double Minv[Q][Q], const dou
 
 /* Perturbation operator Eq. (perturb) summed over the two colours (A_r = A_b = A), with
  * the square of R5:  f_i += A |grad phi| [ w_i (c_i . grad phi)^2 / |grad phi|^2 - B_i ]. */
-void oracle_perturbation(double A, const double *gphi, double *f) {
+void oracle_perturbation(double A, double gphi_cut, const double *gphi, double *f) {
   const double g2 = gphi[0] * gphi[0] + gphi[1] * gphi[1] + gphi[2] * gphi[2];
-  if (g2 < GRAD_PHI_MIN * GRAD_PHI_MIN) return;
+  if (!(g2 > gphi_cut * gphi_cut)) return; /* R7: no normal */
   const double gn = sqrt(g2);
   for (int i = 0; i < Q; i++) {
     const double cg = CV[i][0] * gphi[0] + CV[i][1] * gphi[1] + CV[i][2] * gphi[2];
@@ -296,14 +297,14 @@ void oracle_perturbation(double A, const double *gphi, double *f) {
  *   f^r_i = rho_r/rho f_i + beta rho_r rho_b/rho^2 cos(theta_i) f_i^(e)(rho, 0, alpha_bar)
  *   f^b_i = rho_b/rho f_i - beta rho_r rho_b/rho^2 cos(theta_i) f_i^(e)(rho, 0, alpha_bar)
  * with cos(theta_i) = c_i . grad phi / (|c_i| |grad phi|) and f^(e)(rho,0,a) = rho varphi_i(a). */
-void oracle_recolour(double rho_r, double rho_b, double beta, double alpha_bar, const double *gphi,
-                     const double *f, double *fr, double *fb) {
+void oracle_recolour(double rho_r, double rho_b, double beta, double alpha_bar, double gphi_cut,
+                     const double *gphi, const double *f, double *fr, double *fb) {
   const double rho = rho_r + rho_b;
   const double g2 = gphi[0] * gphi[0] + gphi[1] * gphi[1] + gphi[2] * gphi[2];
   const double gn = sqrt(g2);
   for (int i = 0; i < Q; i++) {
     double cosv = 0.0;
-    if (i != 0 && g2 >= GRAD_PHI_MIN * GRAD_PHI_MIN) {
+    if (i != 0 && g2 > gphi_cut * gphi_cut) { /* R7 */
       const double cg = CV[i][0] * gphi[0] + CV[i][1] * gphi[1] + CV[i][2] * gphi[2];
       cosv = cg / (sqrt((double)shell(i)) * gn);
     }
@@ -476,8 +477,8 @@ void oracle_collide_cell(const oracle *o, const double *fr_in, const double *fb_
   oracle_equilibrium(rr, rb, o->alpha_r, o->alpha_b, u, nubar, grad_rho, feq);
   oracle_forcing_velocity_space(u, F, Fp);
   mrt_collide(o->M, o->Minv, K, f, feq, Fp, fc);
-  oracle_perturbation(o->p.A, grad_phi, fc);
-  oracle_recolour(rr, rb, o->p.beta, abar, grad_phi, fc, fr_out, fb_out);
+  oracle_perturbation(o->p.A, o->p.gphi_cut, grad_phi, fc);
+  oracle_recolour(rr, rb, o->p.beta, abar, o->p.gphi_cut, grad_phi, fc, fr_out, fb_out);
 }
 
 /* Source of the population arriving at (x,y,z) along direction i: returns the source
