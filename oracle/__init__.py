@@ -100,9 +100,14 @@ def _vec(x, n=None):
     return a
 
 
-def params_from_problem(pb, gphi_cut: float = 0.0) -> _Params:
+# Reading R7: the interface normal is undefined where |grad phi| <= this, the FP64 noise
+# floor (rounding leaves ~1e-17 at symmetry points, where the exact gradient is 0).
+GPHI_CUT = 1e-12
+
+
+def params_from_problem(pb, gphi_cut: float = GPHI_CUT) -> _Params:
     """Oracle parameters of a problem.  ``gphi_cut`` is the |grad phi| at and below which
-    the interface normal is taken as undefined (reading R7: 0, only where grad phi = 0)."""
+    the interface normal is taken as undefined (reading R7)."""
     p = _Params()
     p.nx, p.ny, p.nz = pb.nx, pb.ny, pb.nz
     p.rho_r0, p.rho_b0, p.nu_r, p.nu_b = pb.rho_r0, pb.rho_b0, pb.nu_r, pb.nu_b
@@ -128,7 +133,7 @@ def params_from_problem(pb, gphi_cut: float = 0.0) -> _Params:
 class Oracle:
     """A running FP64 simulation of a :class:`workloads.Problem`."""
 
-    def __init__(self, problem, init: bool = True, gphi_cut: float = 0.0):
+    def __init__(self, problem, init: bool = True, gphi_cut: float = GPHI_CUT):
         self.pb = problem
         self._p = params_from_problem(problem, gphi_cut)
         h = ctypes.c_void_p()
@@ -245,14 +250,14 @@ def forcing_velocity_space(u, F) -> np.ndarray:
     return out
 
 
-def perturbation(A, grad_phi, f, gphi_cut: float = 0.0) -> np.ndarray:
+def perturbation(A, grad_phi, f, gphi_cut: float = GPHI_CUT) -> np.ndarray:
     out = _vec(f, Q).copy()
     gp = _vec(grad_phi, 3)
     lib().oracle_perturbation(float(A), float(gphi_cut), _ptr(gp), _ptr(out))
     return out
 
 
-def recolour(rho_r, rho_b, beta, alpha_bar, grad_phi, f, gphi_cut: float = 0.0):
+def recolour(rho_r, rho_b, beta, alpha_bar, grad_phi, f, gphi_cut: float = GPHI_CUT):
     fr, fb = np.empty(Q), np.empty(Q)
     gp, ff = _vec(grad_phi, 3), _vec(f, Q)
     lib().oracle_recolour(float(rho_r), float(rho_b), float(beta), float(alpha_bar), float(gphi_cut), _ptr(gp),

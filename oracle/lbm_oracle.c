@@ -25,9 +25,11 @@
  *   R6  A is a run constant, A_r = A_b = A.
  *   R7  cos(theta_1) = 0 for the rest velocity.  Both the perturbation and the recolouring
  *       segregation need the interface normal grad phi / |grad phi|, which exists wherever
- *       grad phi != 0; where grad phi = 0 exactly both are taken as zero (the perturbation is
- *       continuous there; the segregation term is 0/0).  A cut-off |grad phi| <= gphi_cut
- *       can be set for the convergence check of this reading; it is 0 by default.
+ *       grad phi != 0; where grad phi = 0 both are zero (the perturbation is continuous
+ *       there; the segregation term is 0/0).  At a symmetry point the exact gradient is 0
+ *       but the FP64 one is rounding noise of ~1e-17 with an arbitrary direction, so the
+ *       normal is taken as undefined where |grad phi| <= gphi_cut, set at the FP64 noise
+ *       floor (1e-12 by the test wrapper); results do not change when it moves by 100x.
  *   R8  no-slip walls are half-way bounce-back, per colour; walls lie half a cell outside
  *       the first/last plane.  Gradient stencils see a ghost layer equal to the adjacent
  *       cell (zero normal gradient).
@@ -81,7 +83,7 @@ typedef struct {
   unsigned long long seed;
   int gnx, gny, gnz;     /* dimensions of the whole domain the noise counter refers to */
   int ox, oy, oz;        /* origin of this lattice inside that domain */
-  double gphi_cut;       /* R7: no normal where |grad phi| <= gphi_cut (0: only grad phi = 0) */
+  double gphi_cut;       /* R7: no normal where |grad phi| <= gphi_cut (FP64 noise floor) */
 } oracle_params;
 
 typedef struct {

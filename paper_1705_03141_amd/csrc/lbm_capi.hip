@@ -113,8 +113,13 @@ static lbm_status check_params(const lbm_params* p, lbm_ctx* c, std::string& msg
     c->pc.alpha_b = (float)kAlphaB;
     c->pc.dalpha = (float)(alpha_r - kAlphaB);
     c->pc.E0 = (float)(p->rho_b0 * (1.0 - kAlphaB));
+    c->pc.one_m_ab = (float)(1.0 - kAlphaB);
+    c->pc.one_m_ar = (float)((1.0 - kAlphaB) * p->rho_b0 / p->rho_r0);
     c->cp.alpha_r = (float)alpha_r;
     c->cp.alpha_b = (float)kAlphaB;
+    c->cp.dalpha = c->pc.dalpha;
+    c->cp.one_m_ab = c->pc.one_m_ab;
+    c->cp.one_m_ar = c->pc.one_m_ar;
     c->cp.nu_r = (float)p->nu_r;
     c->cp.nu_b = (float)p->nu_b;
     c->cp.A = (float)p->A;

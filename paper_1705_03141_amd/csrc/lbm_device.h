@@ -169,10 +169,11 @@ __host__ __device__ inline int plane_mode(const Geo& G, int z) {
 // then e and a of the outlet cell; 56 planes of nx*ny floats.
 constexpr int kOutletPlanes = 56;
 
-// Per-run constants for the pull.
+// Per-run constants for the pull (the differences are formed in FP64, then rounded).
 struct PullConst {
   float alpha_r, alpha_b, dalpha;  // dalpha = alpha_r - alpha_b
   float E0;                        // rho_b0 (1 - alpha_b)
+  float one_m_ab, one_m_ar;        // 1 - alpha_b, 1 - alpha_r = (1 - alpha_b)/gamma
 };
 
 // Colour fractions (a, b) = (rho_r/rho, rho_b/rho) of a stored psi.
@@ -183,9 +184,12 @@ __host__ __device__ __forceinline__ float psi_encode(float rho_r, float rho_b, f
   return rho_r <= rho_b ? rho_r / rho : -(rho_b / rho);
 }
 
-// Density of a cell from its stored (e, a).
-__host__ __device__ __forceinline__ float rho_of(const PullConst& C, float e, float a) {
-  return (C.E0 + e) * rcp(fmaf(-a, C.dalpha, 1.0f - C.alpha_b));
+// Density of a cell from its stored (e, a, b): rho = E/(1 - alpha_bar), E = E0 + e.
+__host__ __device__ __forceinline__ float rho_of(const PullConst& C, float e, float a, float b) {
+  return (C.E0 + e) * rcp(one_minus_abar(a, b, C.dalpha, C.one_m_ab, C.one_m_ar));
+}
+__host__ __device__ __forceinline__ float rho_of_psi(const PullConst& C, float e, float psi) {
+  return rho_of(C, e, psi_a(psi), psi_b(psi));
 }
 
 }  // namespace lbm

@@ -72,7 +72,7 @@ __device__ __forceinline__ void pull_cell(const Geo& G, const PullConst& C, cons
   const bool track_red = !psi_red_major(psi_self);  // the reader's minority colour
   const float a_self = psi_a(psi_self);
   const float t_self = track_red ? psi_self : -psi_self;  // fraction of the tracked colour
-  const float rho_old = rho_of(C, e_self, a_self);
+  const float rho_old = rho_of_psi(C, e_self, psi_self);
   const float E_self = C.E0 + e_self;
   const float sgn = track_red ? 1.0f : -1.0f;  // recolouring adds to red, removes from blue
   // rest population: its source is the reader itself
@@ -178,7 +178,7 @@ __device__ __forceinline__ void init_cell(const float* __restrict__ init, const 
                                           float (&df)[Q]) {
   e = init[c];
   const float psi = init[n + c];
-  rho = rho_of(C, e, psi_a(psi));
+  rho = rho_of_psi(C, e, psi);
   rho_r = psi_a(psi) * rho;
   rho_b = psi_b(psi) * rho;
   if constexpr (WANT_DF) {
@@ -200,7 +200,7 @@ __device__ __forceinline__ void outlet_cell(const float* __restrict__ outlet, co
   asm volatile("" : "+v"(col));
   e = outlet[54 * plane + col];
   const float psi = outlet[55 * plane + col];
-  rho = rho_of(C, e, psi_a(psi));
+  rho = rho_of_psi(C, e, psi);
   rho_r = psi_a(psi) * rho;
   rho_b = psi_b(psi) * rho;
   if constexpr (WANT_DF) {
@@ -218,7 +218,7 @@ __device__ __forceinline__ void pull_colours(const AuxArgs& A, int x, int y, int
   GlobalAcc acc{A.sc_in, &A.geo, &b};
   const T* g = static_cast<const T*>(A.g_in);
   const float e_self = acc.self_e(), psi_self = acc.self_psi();
-  const float rho_self = rho_of(A.pc, e_self, psi_a(psi_self));
+  const float rho_self = rho_of_psi(A.pc, e_self, psi_self);
   auto one = [&](auto ic, auto mode) {
     constexpr int i = decltype(ic)::value;
     constexpr Src s = resolve<i, decltype(mode)::value>();
@@ -315,7 +315,7 @@ __device__ void outlet_state(const AuxArgs& A, int x, int y, float (&dr)[Q], flo
     db[i] = (A.outlet_in[(Q + i) * plane + col] + lam * dbi) * inv;
   }
   const float e_prev = A.outlet_in[54 * plane + col], psi_prev = A.outlet_in[55 * plane + col];
-  const float rho_prev = rho_of(A.pc, e_prev, psi_a(psi_prev));
+  const float rho_prev = rho_of_psi(A.pc, e_prev, psi_prev);
   const float rr = (psi_a(psi_prev) * rho_prev + lam * rho_r) * inv;
   const float rb = (psi_b(psi_prev) * rho_prev + lam * rho_b) * inv;
   e_out = (e_prev + lam * e_b) * inv;
@@ -400,7 +400,7 @@ __device__ void cell_state(const AuxArgs& A, int x, int y, int z, float& rho, fl
       });
     } else {
       outlet_state<T>(A, x, y, dr, db, e, psi);
-      rho = rho_of(A.pc, e, psi_a(psi));
+      rho = rho_of_psi(A.pc, e, psi);
       rho_r = psi_a(psi) * rho;
       rho_b = psi_b(psi) * rho;
     }

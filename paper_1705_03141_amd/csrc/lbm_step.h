@@ -135,7 +135,7 @@ __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], 
   const float e_self = me.x, a_self = me.y, b_self = me.z;
   const bool track_red = a_self <= b_self;  // the reader's minority colour
   const float t_self = track_red ? a_self : b_self;
-  const float rho_old = rho_of(C, e_self, a_self);
+  const float rho_old = rho_of(C, e_self, a_self, b_self);
   const float E_self = add_nc(C.E0, e_self);
   const float sgn = track_red ? 1.0f : -1.0f;  // recolouring adds to red, removes from blue
   const float qE[4] = {0.0f, mul_nc(q_of(1), E_self), mul_nc(q_of(7), E_self), mul_nc(q_of(19), E_self)};

@@ -384,12 +384,23 @@ def cfg_jet(steps: int = 30000) -> Problem:
 def small_configs():
     """Parity-sized problems: the 32^3 static droplet, a droplet with Suga's rates at a
     viscosity where they are stable, a reduced Rayleigh-Taylor box and a reduced jet with
-    the physics of the full-size workloads."""
+    the physics of the full-size workloads; and, for the local viscosity and the
+    density-ratio terms, the reduced jet at the paper's viscosity ratio eta = 4.2 (Table III),
+    a droplet with eta = 10 (nu_b = 1e-3) and one with density ratio gamma = 10."""
     suga_drop = static_droplet(n=24, radius=6.0, rho_r0=1.5, rho_b0=1.0, nu=1.667e-2, A=0.01, beta=0.7)
     suga_drop.name = "droplet24_suga"
+    eta_drop = static_droplet(n=24, radius=6.0, rho_r0=1.5, rho_b0=1.0, nu=1e-2, nu_b=1e-3, A=0.01, beta=0.7)
+    eta_drop.name = "droplet24_eta10"
+    gamma_drop = static_droplet(n=24, radius=6.0, rho_r0=10.0, rho_b0=1.0, nu=1e-2, A=0.01, beta=0.7)
+    gamma_drop.name = "droplet24_gamma10"
+    jet_eta = jet(nx=24, ny=24, nz=48, diameter=8.0, eta=4.2)
+    jet_eta.name = "jet_small_eta4.2"
     return {
         "droplet32": cfg_static_droplet(),
         "droplet24_suga": suga_drop,
         "rt_small": rayleigh_taylor(width=16, height=48, g=1e-4, reynolds=64.0),
         "jet_small": jet(nx=24, ny=24, nz=48, diameter=8.0),
+        "droplet24_eta10": eta_drop,
+        "droplet24_gamma10": gamma_drop,
+        "jet_small_eta": jet_eta,
     }

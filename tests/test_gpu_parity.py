@@ -78,14 +78,20 @@ def test_populations_first_steps(O, name):
 
 # ------------------------------------------------------------------ 1000-step parity
 
-# The gamma = 1.5 droplet with the Suga rates is at rest up to spurious currents of ~3e-4:
-# relative to that scale its FP32 velocity error sits at ~1.0e-5 (3e-9 absolute, the rounding
-# floor of O(1e-3) population deviations accumulated over the run), so it is held to 2e-5.
-U_TOL = {"droplet24_suga": 2e-5}
+
+
+# Two static droplets have velocities that are spurious currents only, and there FP32
+# storage of the state alone moves the velocity by about 1e-5 relative or more: rounding the
+# FP64 oracle's state to FP32 after every step gives 2.8e-5 (density ratio 10) and 1.2e-5
+# (printed relaxation rates) after 1000 steps (tests/test_oracle_fp32_floor.py).  Their
+# velocity bar is twice that floor; density keeps the 1e-5 bar.
+U_TOL = {"droplet24_gamma10": 5.6e-5, "droplet24_suga": 2.4e-5}
 
 
 @pytest.mark.parametrize("name,steps", [("droplet32", (200, 1000)), ("droplet24_suga", (300, 1000)),
-                                        ("rt_small", (300, 1000)), ("jet_small", (300, 1000))])
+                                        ("rt_small", (300, 1000)), ("jet_small", (300, 1000)),
+                                        ("jet_small_eta", (300, 1000)), ("droplet24_eta10", (300, 1000)),
+                                        ("droplet24_gamma10", (300, 1000))])
 def test_parity_fields(O, name, steps):
     pb = W.small_configs()[name]
     log(f"[parity] {name} {pb.nx}x{pb.ny}x{pb.nz} steps {steps}")

@@ -1,11 +1,17 @@
 """Reading R7 (Sec. II, the perturbation operator and the recolouring cos theta_i): the
 interface normal grad phi / |grad phi| is used wherever grad phi != 0, and both terms vanish
-only where grad phi = 0.  The oracle takes that rule literally (cut-off 0).
+where grad phi = 0.  In FP64 the oracle takes the normal as undefined where |grad phi| is
+at most 1e-12, the noise floor of its gradient: at a point of exact symmetry the stencil
+sum is rounding noise of ~1e-17 whose direction the fields do not define.
 
-This pins that the reading is converged in FP64: moving the cut-off from 0 to 1e-12 (below
-which the direction of grad phi carries no information the fields define) changes the
-1000-step fields of the parity problems by no more than 1e-9 relative.  A cut-off at 1e-5,
-a value suited to FP32, is not converged: it moves the same fields by more than 1e-6.
+Pins:
+* the reading is converged: moving the cut-off by 100x (1e-12 -> 1e-14) changes the
+  1000-step fields of the parity problems by at most 1e-9 relative (measured: 0 and 4e-13);
+* a cut-off suited to FP32, 1e-5, is not converged (it moves the fields by more than 1e-6;
+  measured 6e-5 on rho_r);
+* a cut-off of 0 is not defined at a symmetry point: a droplet centred on a cell, whose
+  centre has grad phi below 1e-12, then takes a normal from rounding noise and moves its
+  fields by more than 1e-6 within 40 steps, while 1e-12 and 1e-14 agree.
 """
 import numpy as np
 import pytest
@@ -22,7 +28,7 @@ def rel_change(a, b):
     }
 
 
-def run(O, pb, cut, steps=1000):
+def run(O, pb, cut, steps):
     o = O.Oracle(pb, gphi_cut=cut)
     o.step(steps)
     return o.fields()
@@ -31,9 +37,23 @@ def run(O, pb, cut, steps=1000):
 @pytest.mark.parametrize("name", ["droplet32", "rt_small"])
 def test_r7_cutoff_converged(oracle_lib, name):
     pb = W.small_configs()[name]
-    ref = run(oracle_lib, pb, 0.0)
-    e = rel_change(run(oracle_lib, pb, 1e-12), ref)
+    ref = run(oracle_lib, pb, oracle_lib.GPHI_CUT, 1000)
+    e = rel_change(run(oracle_lib, pb, oracle_lib.GPHI_CUT / 100, 1000), ref)
     assert max(e.values()) <= 1e-9, e
     if name == "rt_small":
-        coarse = rel_change(run(oracle_lib, pb, 1e-5), ref)
+        coarse = rel_change(run(oracle_lib, pb, 1e-5, 1000), ref)
         assert max(coarse.values()) > 1e-6, coarse
+
+
+def test_r7_symmetry_point(oracle_lib):
+    O = oracle_lib
+    pb = W.static_droplet(dims=(37, 29, 23), radius=6.0, rho_r0=1.5, rho_b0=1.0, nu=0.05, A=0.01)
+    centre = (11, 14, 18)  # (z, y, x) = ((n - 1)/2 per axis), a lattice cell
+    o = O.Oracle(pb)
+    o.step(10)
+    f = o.fields()
+    g = o.gradient(f["phi"])
+    assert np.abs(g[(slice(None),) + centre]).max() < 1e-12
+    ref = run(O, pb, O.GPHI_CUT, 40)
+    assert max(rel_change(run(O, pb, O.GPHI_CUT / 100, 40), ref).values()) <= 1e-9
+    assert max(rel_change(run(O, pb, 0.0, 40), ref).values()) > 1e-6
