@@ -168,3 +168,52 @@ def test_two_layer_poiseuille_viscosity_contrast(O):
     err = np.abs(ux - exact).max() / np.abs(exact).max()
     print(f"two-layer flow: max relative deviation {err:.3e}")
     assert err < 0.01
+
+
+def test_convective_outflow_weight(O):
+    """The weight lambda of the convective outflow (Sec. IV A, Lou's first-order implicit
+    scheme; reading R11: lambda = u_z of the plane below the outlet after streaming, F/2
+    included).
+
+    One step from a uniform plug flow u = U e_z that a uniform body force F = rho g e_z
+    accelerates.  Colours are passive (gamma = 1, A = 0, beta = 0), the bulk is red and the
+    outlet plane blue.  Momentum gains F per step, so the plane below the outlet holds
+    u_z = (rho U + F + F/2)/rho = U + 1.5 g after the step, and the outlet plane becomes
+    [f(t) + lambda f(N-1, t+1)]/(1 + lambda) colour by colour.  Its red mass is then
+    lambda/(1 + lambda) times the red that arrived below it moving up or sideways (the
+    populations moving down came from the blue outlet), and its blue mass is
+    (1 + lambda S_down)/(1 + lambda), S_down the blue that arrived moving down.  lambda at the
+    old time level (U + g/2) or without F/2 (U + g) is off by ~1 % and fails."""
+    nx, ny, nz = 4, 4, 8
+    U, g = 0.04, 1e-3
+    shape = (nz, ny, nx)
+    rr = np.ones(shape)
+    rb = np.zeros(shape)
+    rr[-1], rb[-1] = 0.0, 1.0
+    u = np.zeros((3,) + shape)
+    u[2] = U
+    pb = W.Problem(name="outflow_weight", nx=nx, ny=ny, nz=nz, rho_r0=1.0, rho_b0=1.0, nu_r=0.05, nu_b=0.05, A=0.0,
+                   beta=0.0, faces=(W.PERIODIC,) * 4 + (W.FREESLIP, W.OUTFLOW), force_model=1, g=(0.0, 0.0, g),
+                   rho_ref=0.0, rho_r=rr, rho_b=rb, u=u)
+    o = O.Oracle(pb)
+    o.step(1)
+    f = o.populations()  # [colour, i, z, y, x]
+    c, _, _ = O.lattice()
+    up = c[:, 2] >= 0
+    down = c[:, 2] < 0
+    below_r = f[0][:, nz - 2]
+    below_b = f[1][:, nz - 2]
+    assert np.abs(below_b[up]).max() == 0.0 and np.abs(below_r[down]).max() == 0.0
+    S_up = below_r[up].sum(0)
+    S_down = below_b[down].sum(0)
+    red_out = f[0][:, nz - 1].sum(0)
+    blue_out = f[1][:, nz - 1].sum(0)
+
+    def predicted(lam):
+        return lam / (1.0 + lam) * S_up, (1.0 + lam * S_down) / (1.0 + lam)
+
+    r, b = predicted(U + 1.5 * g)
+    assert np.abs(red_out - r).max() < 1e-13 and np.abs(blue_out - b).max() < 1e-13
+    for wrong in (U + 0.5 * g, U + g):
+        r, b = predicted(wrong)
+        assert np.abs(red_out - r).max() > 1e-5
