@@ -44,7 +44,9 @@ typedef enum {
  * forms store the deviation of each population from the local rest equilibrium. */
 typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
 
-/* Face rules (Secs. III C, IV A).  x and y faces must be periodic. */
+/* Face rules (Secs. III C, IV A).  The two x faces must be both periodic or both free-slip
+ * (the lateral walls of the jet, Sec. IV A), and likewise the two y faces; each z face takes
+ * any rule (outflow on +z only), periodic only in pairs. */
 typedef enum {
   LBM_PERIODIC = 0,   /* wrap-around streaming and stencil */
   LBM_BOUNCEBACK = 1, /* no-slip wall, half-way bounce-back, half a cell outside the plane */
@@ -121,7 +123,10 @@ lbm_status lbm_get_tiling(const lbm_ctx *ctx, int *tx, int *ty, int *zchunk);
 /* Enqueue nsteps time steps (nsteps >= 0) on the context's stream; returns at once. */
 lbm_status lbm_step(lbm_ctx *ctx, int nsteps);
 
-/* Wait for queued work; reports LBM_EDEVICE if a kernel failed. */
+/* Wait for queued work.  LBM_EDEVICE if a kernel failed; LBM_EUNSTABLE if, since the state
+ * was set, the step kernel met a cell whose pulled density was NaN, infinite or <= 0 (the
+ * check runs on every cell at every step; the flag is cleared by lbm_init_fields and
+ * restored by lbm_load_state). */
 lbm_status lbm_sync(lbm_ctx *ctx);
 
 /* Number of steps taken since lbm_init_fields. */
@@ -135,16 +140,22 @@ enum { LBM_FIELD_RHO_R = 0, LBM_FIELD_RHO_B = 1, LBM_FIELD_UX = 2, LBM_FIELD_UY 
        LBM_FIELD_PHI = 5, LBM_FIELD_P = 6 };
 lbm_status lbm_read_field(lbm_ctx *ctx, int field, double *dst);
 
-/* Same for the box [x0, x0+wx) x [y0, y0+wy) x [z0, z0+wz); dst: wx*wy*wz doubles. */
+/* Same for the box [x0, x0+wx) x [y0, y0+wy) x [z0, z0+wz); dst: wx*wy*wz doubles.
+ * The read-back calls fill dst and then return LBM_EUNSTABLE if the step kernel has flagged
+ * the state (see lbm_sync). */
 lbm_status lbm_read_field_box(lbm_ctx *ctx, int field, int x0, int y0, int z0, int wx, int wy, int wz, double *dst);
 
 /* Pre-collision populations of the current time, per colour: dst holds 2*27*ncells
  * doubles ordered [colour (0 red, 1 blue)][velocity][cell]. */
 lbm_status lbm_read_populations(lbm_ctx *ctx, double *dst);
 
-/* Checkpoint: the opaque device state (populations, scalars, outlet plane, step counter).
- * lbm_state_bytes gives the size; lbm_save_state copies it into host memory dst;
- * lbm_load_state restores it into a context created with the same parameters. */
+/* Checkpoint: the opaque device state (populations, scalars, outlet plane, step counter,
+ * instability flag).  lbm_state_bytes gives the size; lbm_save_state copies it into host
+ * memory dst (bytes >= lbm_state_bytes); lbm_load_state restores it into a context created
+ * with the same parameters.  The first 64 bytes are a header: "LBMD3Q27", the step (int64),
+ * nx, ny, nz, storage, the six face rules and the flag (int32 each); lbm_load_state returns
+ * LBM_EINVAL, leaving the context unchanged, for a buffer that is too small, is not a saved
+ * state, or comes from a lattice of another size, storage or face set. */
 size_t lbm_state_bytes(const lbm_ctx *ctx);
 lbm_status lbm_save_state(lbm_ctx *ctx, void *dst, size_t bytes);
 lbm_status lbm_load_state(lbm_ctx *ctx, const void *src, size_t bytes);
@@ -152,7 +163,8 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *src, size_t bytes);
 /* Global diagnostics with FP64 accumulation on the GPU (deterministic order):
  * mass_r, mass_b: sum of the colour densities; umax: max |u|; p_in, p_out: mean pressure
  * over cells within r_in of (xc, yc, zc) and beyond r_out from it (the static-droplet
- * pressure jump of Sec. III A); nan_cells: cells with a NaN or rho <= 0. */
+ * pressure jump of Sec. III A); nan_cells: cells with a NaN or rho <= 0.  Returns
+ * LBM_EUNSTABLE (out filled) if nan_cells > 0 or the step kernel has flagged the state. */
 typedef struct {
   double mass_r, mass_b, umax, p_in, p_out;
   long long n_in, n_out, nan_cells, step;
@@ -182,6 +194,12 @@ void lbm_destroy(lbm_ctx *ctx);
  *   checkpoint calls; lbm_step on it returns LBM_ESTATE.  NULL for a bad index.
  * lbm_batch_step: nsteps steps of every case (all cases must be initialised and at the same
  *   step, else LBM_ESTATE).  Waits for work queued by the previous call before enqueuing.
+ *   A case the step kernel flags as unstable (see lbm_sync) is not stepped further: within
+ *   the call its workgroups return at once, and later calls leave it out (its step count
+ *   stops).  The batch does not fail for it; LBM_EUNSTABLE only when every case is flagged.
+ * lbm_batch_unstable_cases: waits for the batch's stream, then writes 1 (unstable) or 0 per
+ *   case into flags (ncases ints, or NULL) and returns the number of unstable cases; -1 on a
+ *   device error.
  * lbm_batch_autotune: chooses each case's tile shape by timing every supported shape on a
  *   scratch lattice of the same size and physics for trial_steps steps; the cases' states
  *   are not touched.  Results do not depend on the tile shape.
@@ -195,6 +213,7 @@ int lbm_batch_size(const lbm_batch *batch);
 lbm_status lbm_batch_autotune(lbm_batch *batch, int trial_steps);
 lbm_status lbm_batch_step(lbm_batch *batch, int nsteps);
 lbm_status lbm_batch_sync(lbm_batch *batch);
+int lbm_batch_unstable_cases(lbm_batch *batch, int *flags);
 double lbm_batch_last_step_ms(const lbm_batch *batch);
 const char *lbm_batch_last_error(const lbm_batch *batch);
 void lbm_batch_destroy(lbm_batch *batch);

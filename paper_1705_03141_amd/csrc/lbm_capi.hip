@@ -32,6 +32,7 @@ struct lbm_ctx {
   size_t dbuf_bytes = 0;
   double* diag_part = nullptr;
   double* diag_out = nullptr;
+  int* unstable = nullptr;  // device flag the step kernel sets on a NaN / non-positive density
   long long diag_blocks = 0;
   int cur = 0;              // index of the state holding the current time
   int out_cur = 0;          // index of the outlet record of the latest time
@@ -39,6 +40,7 @@ struct lbm_ctx {
   bool initialised = false;
   int tx = 0, ty = 0, zchunk = 0;  // 0: chosen at the first step (choose_tiling, auto_zchunk)
   bool in_batch = false;           // advanced only by lbm_batch_step
+  bool frozen = false;             // a batch case found unstable: no longer stepped
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   std::string err;
@@ -80,9 +82,11 @@ static lbm_status check_params(const lbm_params* p, lbm_ctx* c, std::string& msg
   if (!(p->nu_r > 0.0) || !(p->nu_b > 0.0)) return msg = "viscosities must be > 0", LBM_EINVAL;
   if (!(p->A >= 0.0)) return msg = "A must be >= 0", LBM_EINVAL;
   if (!(p->beta >= 0.0 && p->beta <= 1.0)) return msg = "beta must lie in [0, 1]", LBM_EINVAL;
-  for (int d = 0; d < 2; ++d)
-    if (p->face[2 * d] != LBM_PERIODIC || p->face[2 * d + 1] != LBM_PERIODIC)
-      return msg = "x and y faces must be periodic", LBM_EINVAL;
+  for (int d = 0; d < 2; ++d) {
+    const int lo_d = p->face[2 * d], hi_d = p->face[2 * d + 1];
+    if (lo_d != hi_d || (lo_d != LBM_PERIODIC && lo_d != LBM_FREESLIP))
+      return msg = "x and y faces must be both periodic or both free-slip", LBM_EINVAL;
+  }
   const int lo = p->face[4], hi = p->face[5];
   if (lo < 0 || lo > 2 || hi < 0 || hi > 3) return msg = "invalid z face rule", LBM_EINVAL;
   if ((lo == LBM_PERIODIC) != (hi == LBM_PERIODIC)) return msg = "periodic z faces must be paired", LBM_EINVAL;
@@ -137,6 +141,8 @@ static lbm_status check_params(const lbm_params* p, lbm_ctx* c, std::string& msg
     G.n = plane * p->nz;
     G.face_lo = lo;
     G.face_hi = hi;
+    G.wall_x = p->face[0] == LBM_FREESLIP ? 1 : 0;
+    G.wall_y = p->face[2] == LBM_FREESLIP ? 1 : 0;
     G.inflow = 0;
     c->elem = p->storage == LBM_F32 ? 4 : 2;
   }
@@ -182,6 +188,8 @@ extern "C" lbm_status lbm_create(const lbm_params* params, void* hip_stream, lbm
   c->diag_blocks = (long long)((n + 255) / 256);
   ok = ok && hipMalloc((void**)&c->diag_part, (size_t)c->diag_blocks * 8 * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->diag_out, 8 * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->unstable, sizeof(int)) == hipSuccess &&
+       hipMemset(c->unstable, 0, sizeof(int)) == hipSuccess;
   ok = ok && hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess;
   if (!ok) {
     lbm_destroy(c);
@@ -202,6 +210,7 @@ extern "C" void lbm_destroy(lbm_ctx* c) {
   if (c->dbuf) (void)hipFree(c->dbuf);
   if (c->diag_part) (void)hipFree(c->diag_part);
   if (c->diag_out) (void)hipFree(c->diag_out);
+  if (c->unstable) (void)hipFree(c->unstable);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
@@ -269,11 +278,13 @@ extern "C" lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_r, const dou
   }
   if (!c->init) LBM_HIP(c, hipMalloc((void**)&c->init, 5 * n * sizeof(float)));
   LBM_HIP(c, hipMemcpyAsync(c->init, h.data(), 5 * n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  LBM_HIP(c, hipMemsetAsync(c->unstable, 0, sizeof(int), c->stream));
   LBM_HIP(c, hipStreamSynchronize(c->stream));
   c->cur = 0;
   c->out_cur = 0;
   c->step = 0;
   c->initialised = true;
+  c->frozen = false;
   return LBM_OK;
 }
 
@@ -327,10 +338,22 @@ static void fill_step_args(const lbm_ctx* c, int cur, int out_cur, StepArgs& s) 
   s.tiles_x = (G.nx + c->tx - 1) / c->tx;
   s.tiles_y = (G.ny + c->ty - 1) / c->ty;
   s.nchunks = (G.nz + c->zchunk - 1) / c->zchunk;
+  s.unstable = c->unstable;
+  s.skip_unstable = c->in_batch ? 1 : 0;
   s.geo = G;
   s.pc = c->pc;
   s.cp = c->cp;
   s.rates = c->rates;
+}
+
+// LBM_EUNSTABLE if the step kernel has flagged a NaN or non-positive density since the state
+// was set (synchronises the context's stream).
+static lbm_status check_unstable(lbm_ctx* c) {
+  int h = 0;
+  LBM_HIP(c, hipMemcpyAsync(&h, c->unstable, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
+  return h ? fail(c, LBM_EUNSTABLE, "the state holds a NaN or a non-positive density (flagged by the step kernel)")
+           : LBM_OK;
 }
 
 static lbm_status enqueue_one(lbm_ctx* c) {
@@ -373,7 +396,7 @@ extern "C" lbm_status lbm_step(lbm_ctx* c, int nsteps) {
 extern "C" lbm_status lbm_sync(lbm_ctx* c) {
   if (!c) return LBM_EINVAL;
   LBM_HIP(c, hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return c->initialised ? check_unstable(c) : LBM_OK;
 }
 
 extern "C" double lbm_last_step_kernel_ms(const lbm_ctx* cc) {
@@ -424,7 +447,7 @@ extern "C" lbm_status lbm_read_field_box(lbm_ctx* c, int field, int x0, int y0, 
     LBM_HIP(c, hipStreamSynchronize(c->stream));
   }
   (void)nb;
-  return LBM_OK;
+  return check_unstable(c);
 }
 
 extern "C" lbm_status lbm_read_field(lbm_ctx* c, int field, double* dst) {
@@ -443,7 +466,7 @@ extern "C" lbm_status lbm_read_populations(lbm_ctx* c, double* dst) {
   if (e != hipSuccess) return hip_fail(c, e, "populations kernel");
   LBM_HIP(c, hipMemcpyAsync(dst, c->dbuf, n * 2 * Q * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   LBM_HIP(c, hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return check_unstable(c);
 }
 
 extern "C" lbm_status lbm_diagnostics(lbm_ctx* c, double xc, double yc, double zc, double r_in, double r_out,
@@ -466,10 +489,22 @@ extern "C" lbm_status lbm_diagnostics(lbm_ctx* c, double xc, double yc, double z
   out->nan_cells = (long long)h[6];
   out->umax = h[7];
   out->step = c->step;
-  return out->nan_cells > 0 ? fail(c, LBM_EUNSTABLE, "state holds NaN or non-positive density") : LBM_OK;
+  if (out->nan_cells > 0) return fail(c, LBM_EUNSTABLE, "state holds NaN or non-positive density");
+  return check_unstable(c);
 }
 
 // ---------------------------------------------------------------- checkpoint
+// Header of a saved state (64 bytes): "LBMD3Q27", the step (int64), then nx, ny, nz, the
+// storage and the six face rules (int32 each), then the instability flag (int32).  A state
+// loads only into a context with the same lattice, storage and faces.
+static void state_header(const lbm_ctx* c, char* h) {
+  std::memcpy(h, "LBMD3Q27", 8);
+  std::memcpy(h + 8, &c->step, sizeof(long long));
+  const int geo[10] = {c->p.nx, c->p.ny, c->p.nz, (int)c->p.storage, c->p.face[0], c->p.face[1],
+                       c->p.face[2], c->p.face[3], c->p.face[4], c->p.face[5]};
+  std::memcpy(h + 16, geo, sizeof(geo));
+}
+
 extern "C" size_t lbm_state_bytes(const lbm_ctx* c) {
   if (!c) return 0;
   const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
@@ -484,9 +519,12 @@ extern "C" lbm_status lbm_save_state(lbm_ctx* c, void* dst, size_t bytes) {
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
   char* p = static_cast<char*>(dst);
+  int flag = 0;
+  LBM_HIP(c, hipMemcpyAsync(&flag, c->unstable, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  LBM_HIP(c, hipStreamSynchronize(c->stream));
   std::memset(p, 0, 64);
-  std::memcpy(p, "LBMD3Q27", 8);
-  std::memcpy(p + 8, &c->step, sizeof(long long));
+  state_header(c, p);
+  std::memcpy(p + 56, &flag, sizeof(int));
   p += 64;
   LBM_HIP(c, hipMemcpyAsync(p, c->g[c->cur], n * Q * c->elem, hipMemcpyDeviceToHost, c->stream));
   p += n * Q * c->elem;
@@ -507,24 +545,34 @@ extern "C" lbm_status lbm_load_state(lbm_ctx* c, const void* src, size_t bytes) 
   if (bytes < lbm_state_bytes(c)) return fail(c, LBM_EINVAL, "buffer too small");
   const char* p = static_cast<const char*>(src);
   if (std::memcmp(p, "LBMD3Q27", 8) != 0) return fail(c, LBM_EINVAL, "not a saved state");
+  char mine[64] = {0};
+  state_header(c, mine);
+  if (std::memcmp(p + 16, mine + 16, 40) != 0)
+    return fail(c, LBM_EINVAL, "the saved state belongs to another lattice (size, storage or faces differ)");
   long long step;
+  int flag = 0;
   std::memcpy(&step, p + 8, sizeof(long long));
+  std::memcpy(&flag, p + 56, sizeof(int));
+  if (step < 0 || (flag != 0 && flag != 1)) return fail(c, LBM_EINVAL, "corrupt state header");
   const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
   p += 64;
-  c->cur = 0;
-  c->out_cur = 0;
-  LBM_HIP(c, hipMemcpyAsync(c->g[0], p, n * Q * c->elem, hipMemcpyHostToDevice, c->stream));
+  // into the buffers of the context's current parity, so that a case of a batch stays in
+  // lock-step with the others
+  LBM_HIP(c, hipMemcpyAsync(c->g[c->cur], p, n * Q * c->elem, hipMemcpyHostToDevice, c->stream));
   p += n * Q * c->elem;
-  LBM_HIP(c, hipMemcpyAsync(c->sc[0], p, n * 5 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  LBM_HIP(c, hipMemcpyAsync(c->sc[c->cur], p, n * 5 * sizeof(float), hipMemcpyHostToDevice, c->stream));
   p += n * 5 * sizeof(float);
   if (!c->init) LBM_HIP(c, hipMalloc((void**)&c->init, n * 5 * sizeof(float)));
   LBM_HIP(c, hipMemcpyAsync(c->init, p, n * 5 * sizeof(float), hipMemcpyHostToDevice, c->stream));
   p += n * 5 * sizeof(float);
   if (c->geo.face_hi == FACE_OUTFLOW)
-    LBM_HIP(c, hipMemcpyAsync(c->outlet[0], p, plane * kOutletPlanes * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(c, hipMemcpyAsync(c->outlet[c->out_cur], p, plane * kOutletPlanes * sizeof(float), hipMemcpyHostToDevice,
+                              c->stream));
+  LBM_HIP(c, hipMemcpyAsync(c->unstable, &flag, sizeof(int), hipMemcpyHostToDevice, c->stream));
   LBM_HIP(c, hipStreamSynchronize(c->stream));
   c->step = step;
   c->initialised = true;
+  c->frozen = flag != 0;
   return LBM_OK;
 }
 
@@ -535,6 +583,7 @@ extern "C" lbm_status lbm_load_state(lbm_ctx* c, const void* src, size_t bytes) 
 // lbm_batch_step call.
 struct BatchGroup {
   int storage = 0, tx = 0, ty = 0;
+  bool lat = false;                     // lateral free-slip walls (a separate kernel instance)
   std::vector<int> cases;               // indices into lbm_batch::c
   StepArgs* d_args[2] = {nullptr, nullptr};  // device tables for parity 0 and 1
   int* d_first = nullptr;               // device block offsets (ncases + 1)
@@ -657,15 +706,18 @@ static lbm_status build_groups(lbm_batch* b) {
   free_groups(b);
   for (int k = 0; k < (int)b->c.size(); ++k) {
     const lbm_ctx* c = b->c[k];
+    if (c->frozen) continue;
     BatchGroup* g = nullptr;
+    const bool lat = c->geo.wall_x || c->geo.wall_y;
     for (auto& x : b->groups)
-      if (x.storage == (int)c->p.storage && x.tx == c->tx && x.ty == c->ty) g = &x;
+      if (x.storage == (int)c->p.storage && x.tx == c->tx && x.ty == c->ty && x.lat == lat) g = &x;
     if (!g) {
       b->groups.emplace_back();
       g = &b->groups.back();
       g->storage = (int)c->p.storage;
       g->tx = c->tx;
       g->ty = c->ty;
+      g->lat = lat;
     }
     g->cases.push_back(k);
   }
@@ -697,6 +749,7 @@ static lbm_status build_groups(lbm_batch* b) {
   // outlet and inflow work per storage type (an outflow lattice's record shares its parity)
   for (int k = 0; k < (int)b->c.size(); ++k) {
     const lbm_ctx* c = b->c[k];
+    if (c->frozen) continue;
     for (int which = 0; which < 2; ++which) {
       const bool has = which == 0 ? c->geo.face_hi == FACE_OUTFLOW : (bool)c->geo.inflow;
       if (!has) continue;
@@ -752,24 +805,46 @@ static lbm_status build_groups(lbm_batch* b) {
   return LBM_OK;
 }
 
+// Reads the cases' instability flags (after the batch's stream has drained) and freezes the
+// flagged cases: they are left out of every later launch.  Returns the number of unstable
+// cases, or -1 if a copy failed.
+static int refresh_unstable(lbm_batch* b) {
+  int count = 0;
+  for (lbm_ctx* c : b->c) {
+    if (!c->frozen && c->initialised) {
+      int h = 0;
+      if (hipMemcpy(&h, c->unstable, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+      c->frozen = h != 0;
+    }
+    count += c->frozen ? 1 : 0;
+  }
+  return count;
+}
+
 extern "C" lbm_status lbm_batch_step(lbm_batch* b, int nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (nsteps == 0) return LBM_OK;
-  const lbm_ctx* c0 = b->c[0];
-  for (const lbm_ctx* c : b->c) {
+  for (const lbm_ctx* c : b->c)
     if (!c->initialised) return batch_fail(b, LBM_ESTATE, "every case needs lbm_init_fields before lbm_batch_step");
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "stream synchronisation failed");
+  if (refresh_unstable(b) < 0) return batch_fail(b, LBM_EDEVICE, "reading the instability flags failed");
+  std::vector<lbm_ctx*> active;
+  for (lbm_ctx* c : b->c)
+    if (!c->frozen) active.push_back(c);
+  if (active.empty()) return batch_fail(b, LBM_EUNSTABLE, "every case of the batch is unstable");
+  const lbm_ctx* c0 = active[0];
+  for (const lbm_ctx* c : active) {
     // the outlet record of an outflow lattice flips with its state, so both share the parity
     if (c->step != c0->step || c->cur != c0->cur || (c->geo.face_hi == FACE_OUTFLOW && c->out_cur != c->cur))
       return batch_fail(b, LBM_ESTATE, "the cases of a batch must be at the same step");
   }
-  if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "stream synchronisation failed");
   batch_tiling(b);
   lbm_status st = build_groups(b);
   if (st != LBM_OK) return st;
   if (hipEventRecord(b->ev0, b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "event record failed");
   for (int k = 0; k < nsteps; ++k) {
-    const int par = b->c[0]->cur;
-    const long long step = b->c[0]->step;
+    const int par = active[0]->cur;
+    const long long step = active[0]->step;
     const bool init = step == 0;
     for (const auto& g : b->outlets) {
       const hipError_t e =
@@ -778,7 +853,7 @@ extern "C" lbm_status lbm_batch_step(lbm_batch* b, int nsteps) {
     }
     for (const auto& g : b->groups) {
       const hipError_t e = launch_batch(g.storage, g.d_args[par], g.d_first, (int)g.cases.size(), g.nblocks, init,
-                                        g.tx, g.ty, b->stream);
+                                        g.tx, g.ty, g.lat, b->stream);
       if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("batch step kernel: ") + hipGetErrorString(e));
     }
     for (const auto& g : b->inflows) {
@@ -786,7 +861,7 @@ extern "C" lbm_status lbm_batch_step(lbm_batch* b, int nsteps) {
           launch_batch_inflow(g.storage, g.d_step[par], g.d_first, (int)g.cases.size(), g.nblocks, step, b->stream);
       if (e != hipSuccess) return batch_fail(b, LBM_EDEVICE, std::string("inflow kernel: ") + hipGetErrorString(e));
     }
-    for (lbm_ctx* c : b->c) {
+    for (lbm_ctx* c : active) {
       c->cur = 1 - c->cur;
       if (c->geo.face_hi == FACE_OUTFLOW) c->out_cur = 1 - c->out_cur;
       c->step++;
@@ -795,6 +870,22 @@ extern "C" lbm_status lbm_batch_step(lbm_batch* b, int nsteps) {
   if (hipEventRecord(b->ev1, b->stream) != hipSuccess) return batch_fail(b, LBM_EDEVICE, "event record failed");
   b->last_ms = -(double)nsteps;
   return LBM_OK;
+}
+
+extern "C" int lbm_batch_unstable_cases(lbm_batch* b, int* flags) {
+  if (!b) return -1;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) {
+    batch_fail(b, LBM_EDEVICE, "stream synchronisation failed");
+    return -1;
+  }
+  const int count = refresh_unstable(b);
+  if (count < 0) {
+    batch_fail(b, LBM_EDEVICE, "reading the instability flags failed");
+    return -1;
+  }
+  if (flags)
+    for (size_t k = 0; k < b->c.size(); ++k) flags[k] = b->c[k]->frozen ? 1 : 0;
+  return count;
 }
 
 extern "C" lbm_status lbm_batch_sync(lbm_batch* b) {

@@ -41,6 +41,8 @@ __host__ __device__ constexpr int dir_of(int cx, int cy, int cz) {
   return r;
 }
 __host__ __device__ constexpr int opposite(int i) { return dir_of(-CX[i], -CY[i], -CZ[i]); }
+__host__ __device__ constexpr int mirror_x(int i) { return dir_of(-CX[i], CY[i], CZ[i]); }
+__host__ __device__ constexpr int mirror_y(int i) { return dir_of(CX[i], -CY[i], CZ[i]); }
 __host__ __device__ constexpr int mirror_z(int i) { return dir_of(CX[i], CY[i], -CZ[i]); }
 
 // varphi_i(alpha) = (1 - alpha) q_i for i >= 1 (Eq. (varphi_ik)); q = 2/19, 1/38, 1/152 by shell.

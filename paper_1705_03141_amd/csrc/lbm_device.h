@@ -68,7 +68,8 @@ struct Geo {
   int nx, ny, nz;
   int plane;                 // nx ny
   long long n;               // nx ny nz
-  int face_lo, face_hi;      // rules of the -z and +z faces (x, y are periodic)
+  int face_lo, face_hi;      // rules of the -z and +z faces
+  int wall_x, wall_y;        // 1: free-slip walls on both faces of that axis, 0: periodic
   int inflow;                // inflow disk on z = 0
   float xc, yc, r2;          // disk centre and squared radius
   float rho_r0;              // density emitted by the inflow
@@ -154,6 +155,43 @@ __host__ __device__ constexpr Src resolve() {
     }
   }
   return s;
+}
+
+// The source of population I at a cell (x, y) of a plane in pull mode MODE, with the lateral
+// walls of G (reading R9 on the x and y faces): where the source would lie beyond a free-slip
+// wall, the population comes from the boundary cell itself along that axis, with the normal
+// component of its velocity reversed (the tangential shift is kept).  A bounce-back of the z
+// rule takes precedence, as its source is the cell itself.
+struct RSrc {
+  int dx, dy, dz, j, ccx, ccy, ccz;
+};
+
+template <int I, int MODE>
+__device__ __forceinline__ RSrc resolve_at(const Geo& G, int x, int y) {
+  constexpr Src s = resolve<I, MODE>();
+  RSrc r{s.dx, s.dy, s.dz, s.j, s.ccx, s.ccy, s.ccz};
+  if constexpr (s.dx != 0 || s.dy != 0) {
+    const bool rx = G.wall_x && ((s.dx == -1 && x == 0) || (s.dx == 1 && x == G.nx - 1));
+    const bool ry = G.wall_y && ((s.dy == -1 && y == 0) || (s.dy == 1 && y == G.ny - 1));
+    constexpr int jx = mirror_x(s.j), jy = mirror_y(s.j), jxy = mirror_x(mirror_y(s.j));
+    if (rx) {
+      r.dx = 0;
+      r.ccx = -s.ccx;
+    }
+    if (ry) {
+      r.dy = 0;
+      r.ccy = -s.ccy;
+    }
+    r.j = rx ? (ry ? jxy : jx) : (ry ? jy : s.j);
+  }
+  return r;
+}
+
+// Lateral wall flags of a cell: bit 0 at a -x wall, 1 at a +x wall, 2 at a -y wall, 3 at a
+// +y wall.
+__device__ __forceinline__ int wall_flags(const Geo& G, int x, int y) {
+  return (G.wall_x && x == 0 ? 1 : 0) | (G.wall_x && x == G.nx - 1 ? 2 : 0) | (G.wall_y && y == 0 ? 4 : 0) |
+         (G.wall_y && y == G.ny - 1 ? 8 : 0);
 }
 
 // Pull mode of plane z.

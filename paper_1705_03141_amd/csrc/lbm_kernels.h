@@ -31,6 +31,8 @@ struct StepArgs {
   long long step;
   int init_mode;
   int zchunk, tiles_x, tiles_y, nchunks;
+  int* unstable;         // set to 1 by a cell whose density is NaN, infinite or <= 0
+  int skip_unstable;     // 1: workgroups of a flagged lattice return at once (batches)
   Geo geo;
   PullConst pc;
   CollideParams cp;
@@ -62,7 +64,7 @@ template <typename T>
 hipError_t launch_inflow_T(const StepArgs& a, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_T(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int tx, int ty,
-                          hipStream_t s);
+                          bool lat, hipStream_t s);
 template <typename T>
 int step_resident_blocks_T(int tx, int ty, int device);
 template <typename T>
@@ -85,10 +87,10 @@ hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, lon
 bool step_tiling_supported(int tx, int ty);
 hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream_t s);
 // One step of several lattices in one launch: cases (device array of ncases argument blocks,
-// all with the same storage and tile shape), first (device, ncases + 1 block offsets, each a
-// multiple of 8), nblocks = first[ncases].
+// all with the same storage, tile shape and lateral rule: lat = free-slip x or y walls),
+// first (device, ncases + 1 block offsets, each a multiple of 8), nblocks = first[ncases].
 hipError_t launch_batch(int storage, const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
-                        int tx, int ty, hipStream_t s);
+                        int tx, int ty, bool lat, hipStream_t s);
 // Inflow sites of plane z = 0 written into the step's output state (after launch_step).
 hipError_t launch_inflow(int storage, const StepArgs& a, hipStream_t s);
 // Workgroups of the step kernel that fit on the device at once (0 if unknown).

@@ -30,6 +30,11 @@ struct Nbr {
   int zs[3];
   int row[3];
   int xs[3];
+  int x, y;
+  // entries at a run-time offset d in {-1, 0, 1} (selects, not indexed loads)
+  __device__ __forceinline__ int z_at(int d) const { return d < 0 ? zs[0] : (d > 0 ? zs[2] : zs[1]); }
+  __device__ __forceinline__ int row_at(int d) const { return d < 0 ? row[0] : (d > 0 ? row[2] : row[1]); }
+  __device__ __forceinline__ int x_at(int d) const { return d < 0 ? xs[0] : (d > 0 ? xs[2] : xs[1]); }
 };
 
 __device__ __forceinline__ Nbr neighbours(const Geo& G, int x, int y, int z) {
@@ -44,6 +49,8 @@ __device__ __forceinline__ Nbr neighbours(const Geo& G, int x, int y, int z) {
   b.xs[0] = x == 0 ? G.nx - 1 : x - 1;
   b.xs[1] = x;
   b.xs[2] = x == G.nx - 1 ? 0 : x + 1;
+  b.x = x;
+  b.y = y;
   return b;
 }
 
@@ -51,8 +58,8 @@ __device__ __forceinline__ Nbr neighbours(const Geo& G, int x, int y, int z) {
 template <typename T>
 __device__ __forceinline__ float load_pop(const Geo& G, const T* __restrict__ g, const Nbr& b, int j, int dx, int dy,
                                           int dz) {
-  const T* slab = g + (size_t)(b.zs[dz + 1] * Q + j) * (size_t)G.plane;
-  return Codec<T>::dec(slab[b.row[dy + 1] + b.xs[dx + 1]]);
+  const T* slab = g + (size_t)(b.z_at(dz) * Q + j) * (size_t)G.plane;
+  return Codec<T>::dec(slab[b.row_at(dy) + b.x_at(dx)]);
 }
 
 // Pull of one cell in a plane of pull mode MODE.  Scalars of the source cells come from
@@ -81,14 +88,15 @@ __device__ __forceinline__ void pull_cell(const Geo& G, const PullConst& C, cons
   if constexpr (WANT_DF) df[0] = d_rho;
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    constexpr Src s = resolve<i, MODE>();
+    constexpr Src s0 = resolve<i, MODE>();
+    const RSrc s = resolve_at<i, MODE>(G, b.x, b.y);
     const float gv = load_pop<T>(G, g, b, s.j, s.dx, s.dy, s.dz);
     const float de = acc.e(s.dx, s.dy, s.dz) - e_self, psi = acc.psi(s.dx, s.dy, s.dz);
     const float t = track_red ? psi_a(psi) : psi_b(psi);
     float cw = 0.0f;  // c_j . w of the source, only the non-zero components
-    if constexpr (s.ccx != 0) cw += (float)s.ccx * acc.w(0, s.dx, s.dy, s.dz);
-    if constexpr (s.ccy != 0) cw += (float)s.ccy * acc.w(1, s.dx, s.dy, s.dz);
-    if constexpr (s.ccz != 0) cw += (float)s.ccz * acc.w(2, s.dx, s.dy, s.dz);
+    if constexpr (s0.ccx != 0) cw += (float)s.ccx * acc.w(0, s.dx, s.dy, s.dz);
+    if constexpr (s0.ccy != 0) cw += (float)s.ccy * acc.w(1, s.dx, s.dy, s.dz);
+    if constexpr (s0.ccz != 0) cw += (float)s.ccz * acc.w(2, s.dx, s.dy, s.dz);
     const float d = gv + q_of(i) * de;
     d_rho += d;
     d_t += t * d + q_of(i) * E_self * (t - t_self) + sgn * qc_of(i) * cw;
@@ -124,7 +132,7 @@ struct GlobalAcc {
   const Geo* G;
   const Nbr* b;
   __device__ __forceinline__ float val(int k, int dx, int dy, int dz) const {
-    return sc[(size_t)(b->zs[dz + 1] * 5 + k) * (size_t)G->plane + b->row[dy + 1] + b->xs[dx + 1]];
+    return sc[(size_t)(b->z_at(dz) * 5 + k) * (size_t)G->plane + b->row_at(dy) + b->x_at(dx)];
   }
   __device__ __forceinline__ float self_e() const { return val(0, 0, 0, 0); }
   __device__ __forceinline__ float self_psi() const { return val(1, 0, 0, 0); }
@@ -221,7 +229,8 @@ __device__ __forceinline__ void pull_colours(const AuxArgs& A, int x, int y, int
   const float rho_self = rho_of_psi(A.pc, e_self, psi_self);
   auto one = [&](auto ic, auto mode) {
     constexpr int i = decltype(ic)::value;
-    constexpr Src s = resolve<i, decltype(mode)::value>();
+    constexpr Src s0 = resolve<i, decltype(mode)::value>();
+    const RSrc s = resolve_at<i, decltype(mode)::value>(G, x, y);
     const float gv = load_pop<T>(G, g, b, s.j, s.dx, s.dy, s.dz);
     if constexpr (i == 0) {
       const float f0 = gv + rho_self - (A.pc.E0 + e_self);  // g_0 + rho alpha_bar
@@ -230,9 +239,9 @@ __device__ __forceinline__ void pull_colours(const AuxArgs& A, int x, int y, int
     } else {
       const float fi = gv + q_of(i) * (A.pc.E0 + acc.e(s.dx, s.dy, s.dz));
       float cw = 0.0f;
-      if constexpr (s.ccx != 0) cw += (float)s.ccx * acc.w(0, s.dx, s.dy, s.dz);
-      if constexpr (s.ccy != 0) cw += (float)s.ccy * acc.w(1, s.dx, s.dy, s.dz);
-      if constexpr (s.ccz != 0) cw += (float)s.ccz * acc.w(2, s.dx, s.dy, s.dz);
+      if constexpr (s0.ccx != 0) cw += (float)s.ccx * acc.w(0, s.dx, s.dy, s.dz);
+      if constexpr (s0.ccy != 0) cw += (float)s.ccy * acc.w(1, s.dx, s.dy, s.dz);
+      if constexpr (s0.ccz != 0) cw += (float)s.ccz * acc.w(2, s.dx, s.dy, s.dz);
       const float psi = acc.psi(s.dx, s.dy, s.dz);
       fr[i] = psi_a(psi) * fi + qc_of(i) * cw;
       fb[i] = psi_b(psi) * fi - qc_of(i) * cw;

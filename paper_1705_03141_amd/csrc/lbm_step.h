@@ -97,15 +97,34 @@ __device__ __forceinline__ void column_offsets(const Geo& G, int x, int y, unsig
     for (int a = 0; a < 3; ++a) o[b][a] = (unsigned)((ys[b] * G.nx + xs[a]) * (int)sizeof(T));
 }
 
+// Lateral reflection of a source offset at a cell with wall flags wf (wall_flags): true where
+// the source (dx, dy) lies beyond a free-slip wall in x (AXIS 0) or y (AXIS 1).
+template <int AXIS, int D>
+__device__ __forceinline__ bool reflects(int wf) {
+  if constexpr (D == 0) return false;
+  constexpr int bit = (AXIS == 0 ? 0 : 2) + (D < 0 ? 0 : 1);
+  return (wf >> bit) & 1;
+}
+
 // Issue the 27 population loads of a pull in mode MODE.  slab[k] covers the 27 population
-// planes of source plane z - 1 + k; the raw word of direction i is left in ld[i].
-template <typename T, int MODE>
-__device__ __forceinline__ void issue_pull(const rsrc_t (&slab)[3], int plane_bytes, const unsigned (&o)[3][3],
+// planes of source plane z - 1 + k; the raw word of direction i is left in ld[i].  With
+// lateral walls (LAT) a source beyond a wall is the boundary cell and the mirrored population
+// (reading R9), chosen per lane: its population plane then enters the per-lane offset.
+template <typename T, int MODE, bool LAT>
+__device__ __forceinline__ void issue_pull(const rsrc_t (&slab)[3], int plane_bytes, const unsigned (&o)[3][3], int wf,
                                            typename Word<T>::W (&ld)[Q]) {
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     constexpr Src s = resolve<i, MODE>();
-    ld[i] = Word<T>::load(slab[s.dz + 1], o[s.dy + 1][s.dx + 1], s.j * plane_bytes);
+    if constexpr (!LAT || (s.dx == 0 && s.dy == 0)) {
+      ld[i] = Word<T>::load(slab[s.dz + 1], o[s.dy + 1][s.dx + 1], s.j * plane_bytes);
+    } else {
+      const bool rx = reflects<0, s.dx>(wf), ry = reflects<1, s.dy>(wf);
+      constexpr int jx = mirror_x(s.j), jy = mirror_y(s.j), jxy = mirror_x(mirror_y(s.j));
+      const unsigned col = rx ? (ry ? o[1][1] : o[s.dy + 1][1]) : (ry ? o[1][s.dx + 1] : o[s.dy + 1][s.dx + 1]);
+      const int j = rx ? (ry ? jxy : jx) : (ry ? jy : s.j);
+      ld[i] = Word<T>::load(slab[s.dz + 1], col + (unsigned)(j * plane_bytes), 0);
+    }
   });
 }
 
@@ -127,9 +146,9 @@ __device__ __forceinline__ float div_nc(float a, float b) {
   return a / b;
 }
 
-template <typename T, int MODE, bool WANT_DF, int SX>
+template <typename T, int MODE, bool WANT_DF, int SX, bool LAT>
 __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], const float4* const (&S)[3], const float2* const (&W)[3],
-                                            int idx0, const PullConst& C, float& rho, float& rho_r, float& rho_b,
+                                            int idx0, int wf, const PullConst& C, float& rho, float& rho_r, float& rho_b,
                                             float& e_new, float (&df)[Q], float& shift_out, float& drho_out) {
   const float4 me = S[1][idx0 + SX + 1];
   const float e_self = me.x, a_self = me.y, b_self = me.z;
@@ -153,12 +172,23 @@ __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], 
     constexpr int off = (s.dy + 1) * SX + s.dx + 1;
     constexpr int sh = shell_of(i);
     constexpr bool self_src = s.dx == 0 && s.dy == 0 && s.dz == 0;  // bounce-back
-    const float4 src = S[s.dz + 1][idx0 + off];
-    const float2 w = W[s.dz + 1][idx0 + off];
+    constexpr bool lat = LAT && (s.dx != 0 || s.dy != 0);
+    // lateral wall: the source is the boundary cell along a reflected axis, and the velocity
+    // component normal to that wall is reversed
+    bool rx = false, ry = false;
+    int offl = off;
+    if constexpr (lat) {
+      rx = reflects<0, s.dx>(wf);
+      ry = reflects<1, s.dy>(wf);
+      offl = ((ry ? 0 : s.dy) + 1) * SX + (rx ? 0 : s.dx) + 1;
+    }
+    const float4 src = S[s.dz + 1][idx0 + offl];
+    const float2 w = W[s.dz + 1][idx0 + offl];
     // c_j . w of the source from its non-zero components (a sum started at 0.0f would cost
     // one more add: 0 + x is not folded because of the sign of zero)
-    const float wy = s.ccy > 0 ? w.x : -w.x, wz = s.ccz > 0 ? w.y : -w.y;
-    float cw = s.ccx != 0 ? (s.ccx > 0 ? src.w : -src.w) : (s.ccy != 0 ? wy : wz);
+    const bool px = (s.ccx > 0) != rx, py = (s.ccy > 0) != ry;
+    const float wy = py ? w.x : -w.x, wz = s.ccz > 0 ? w.y : -w.y;
+    float cw = s.ccx != 0 ? (px ? src.w : -src.w) : (s.ccy != 0 ? wy : wz);
     if constexpr (s.ccx != 0 && s.ccy != 0) cw = add_nc(cw, wy);
     if constexpr ((s.ccx != 0 || s.ccy != 0) && s.ccz != 0) cw = add_nc(cw, wz);
     float d, inc;
@@ -229,7 +259,7 @@ struct PlaneState {
   }
 };
 
-template <typename T, int TX, int TY, bool INIT>
+template <typename T, int TX, int TY, bool INIT, bool LAT>
 #ifndef LBM_STEP_WAVES_PER_EU
 #define LBM_STEP_WAVES_PER_EU 2
 #endif
@@ -262,6 +292,9 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   const int ntiles = A.tiles_x * A.tiles_y;
   const int chunk = L / ntiles, tile = L - chunk * ntiles;
   if (chunk >= A.nchunks) return;  // padding block of a batch (the whole block leaves)
+  // a lattice of a batch that went unstable is not stepped further (the flag is read once per
+  // workgroup, before any barrier; the whole workgroup leaves)
+  if (A.skip_unstable && __hip_atomic_load(A.unstable, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const int tyi = tile / A.tiles_x, txi = tile - tyi * A.tiles_x;
   const int x0 = txi * TX, y0 = tyi * TY;
   const int z0 = chunk * A.zchunk, z1 = min(z0 + A.zchunk, G.nz);
@@ -280,6 +313,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   const int rgx = wrap(x0 + rx, G.nx), rgy = wrap(y0 + ry, G.ny);
   const int rcol = rgy * G.nx + rgx;
   const int sR = (ry + 2) * SX + rx + 2, dR = (ry + 1) * DX + rx + 1;
+  // lateral wall flags of the own and the ring cell (0 without lateral walls)
+  const int wfI = LAT ? wall_flags(G, gx, gy) : 0, wfR = LAT ? wall_flags(G, rgx, rgy) : 0;
   // staged cells
   unsigned stOff[KS];  // byte offsets in a scalar plane
 #pragma unroll
@@ -355,8 +390,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
       column_offsets<T>(G, ax, ay, oI);
       column_offsets<T>(G, arx, ary, oR);
       with_mode(mode, [&](auto M) {
-        if (ringer) issue_pull<T, decltype(M)::value>(slab, pb, oR, ldR);
-        issue_pull<T, decltype(M)::value>(slab, pb, oI, ldI);
+        if (ringer) issue_pull<T, decltype(M)::value, LAT>(slab, pb, oR, wfR, ldR);
+        issue_pull<T, decltype(M)::value, LAT>(slab, pb, oI, wfI, ldI);
       });
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -383,7 +418,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           outlet_cell<false>(A.outlet, A.pc, plane, rcol, r_rho, r_r, r_b, r_e, r_df);
         } else {
           with_mode(mode, [&](auto M) {
-            finish_pull<T, decltype(M)::value, false, SX>(ldR, S, W, bR, A.pc, r_rho, r_r, r_b, r_e, r_df, r_sh, r_dr);
+            finish_pull<T, decltype(M)::value, false, SX, LAT>(ldR, S, W, bR, wfR, A.pc, r_rho, r_r, r_b, r_e, r_df,
+                                                               r_sh, r_dr);
           });
         }
         if (is_inflow(G, rgx, rgy, zq)) {
@@ -402,8 +438,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
         nxt.shift = nxt.drho = 0.0f;
       } else {
         with_mode(mode, [&](auto M) {
-          finish_pull<T, decltype(M)::value, true, SX>(ldI, S, W, bI, A.pc, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e,
-                                                       nxt.df, nxt.shift, nxt.drho);
+          finish_pull<T, decltype(M)::value, true, SX, LAT>(ldI, S, W, bI, wfI, A.pc, nxt.rho, nxt.rho_r, nxt.rho_b,
+                                                            nxt.e, nxt.df, nxt.shift, nxt.drho);
         });
       }
       if (is_inflow(G, gx, gy, zq)) {  // R10: inflow sites are pure red at rho_r0
@@ -437,13 +473,16 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           int b0 = dI - DX - 1;
           asm volatile("" : "+v"(b0));
           const int slots[3] = {sm, s0, sp};
+          // beyond a lateral wall the stencil sees the boundary cell (reading R9)
+          const int xo[3] = {(wfI & 1) ? 1 : 0, 1, (wfI & 2) ? 1 : 2};
+          const int yo[3] = {(wfI & 4) ? DX : 0, DX, (wfI & 8) ? DX : 2 * DX};
 #pragma unroll
           for (int dz = 0; dz < 3; ++dz) {
 #pragma unroll
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
               for (int dx = 0; dx < 3; ++dx) {
-                const float4 v = sD[slots[dz]][b0 + dy * DX + dx];
+                const float4 v = sD[slots[dz]][b0 + yo[dy] + xo[dx]];
                 vp[dz][dy][dx] = red_minor ? v.x : v.y;
                 vr[dz][dy][dx] = v.z;
               }
@@ -456,6 +495,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           gp[1] *= two;
           gp[2] *= two;
         }
+        // instability: a NaN anywhere in the pulled populations reaches rho
+        if (!(cur.rho > 0.0f && cur.rho < 3.0e38f)) *A.unstable = 1;
         CellOut o;
         collide_cell(A.cp, A.rates, cur.df, cur.shift, cur.drho, cur.rho, cur.rho_r, cur.rho_b, gp, gr, o);
 #pragma unroll
@@ -476,14 +517,14 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   }
 }
 
-template <typename T, int TX, int TY, bool INIT>
+template <typename T, int TX, int TY, bool INIT, bool LAT>
 __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU) step_kernel(const StepArgs A) {
-  step_body<T, TX, TY, INIT>(A, (int)blockIdx.x, (int)gridDim.x);
+  step_body<T, TX, TY, INIT, LAT>(A, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Many lattices in one launch: case c owns blocks [first[c], first[c+1]) of the grid, each
 // range padded to a multiple of 8 blocks so that the XCD-aware numbering holds per case.
-template <typename T, int TX, int TY, bool INIT>
+template <typename T, int TX, int TY, bool INIT, bool LAT>
 __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU)
     batch_step_kernel(const StepArgs* __restrict__ cases, const int* __restrict__ first, int ncases) {
   const int b = (int)blockIdx.x;
@@ -495,7 +536,7 @@ __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU)
     else
       hi = mid;
   }
-  step_body<T, TX, TY, INIT>(cases[lo], b - first[lo], first[lo + 1] - first[lo]);
+  step_body<T, TX, TY, INIT, LAT>(cases[lo], b - first[lo], first[lo + 1] - first[lo]);
 }
 
 // Inflow sites (R10) after a step: each emits the red equilibrium at rho_r0 and u_in(1 + eps xi)
@@ -545,43 +586,57 @@ __global__ void __launch_bounds__(256)
 }
 
 // ================================================================== launchers
-template <typename T, int TX, int TY>
-hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
+template <typename T, int TX, int TY, bool LAT>
+hipError_t launch_step_lat(const StepArgs& a, hipStream_t s) {
   const long long blocks = (long long)a.tiles_x * a.tiles_y * a.nchunks;
   if (a.init_mode)
-    hipLaunchKernelGGL((step_kernel<T, TX, TY, true>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<T, TX, TY, true, LAT>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
   else
-    hipLaunchKernelGGL((step_kernel<T, TX, TY, false>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<T, TX, TY, false, LAT>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
+  return hipGetLastError();
+}
+
+// The step kernel with lateral free-slip walls is a separate instance: lattices with periodic
+// sides keep the plain pull.
+template <typename T, int TX, int TY>
+hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
+  return (a.geo.wall_x || a.geo.wall_y) ? launch_step_lat<T, TX, TY, true>(a, s) : launch_step_lat<T, TX, TY, false>(a, s);
+}
+
+template <typename T, int TX, int TY, bool LAT>
+hipError_t launch_batch_lat(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
+                            hipStream_t s) {
+  if (init)
+    hipLaunchKernelGGL((batch_step_kernel<T, TX, TY, true, LAT>), dim3((unsigned)nblocks), dim3(TX * TY), 0, s, cases,
+                       first, ncases);
+  else
+    hipLaunchKernelGGL((batch_step_kernel<T, TX, TY, false, LAT>), dim3((unsigned)nblocks), dim3(TX * TY), 0, s, cases,
+                       first, ncases);
   return hipGetLastError();
 }
 
 template <typename T, int TX, int TY>
-hipError_t launch_batch_tile(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
+hipError_t launch_batch_tile(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, bool lat,
                              hipStream_t s) {
-  if (init)
-    hipLaunchKernelGGL((batch_step_kernel<T, TX, TY, true>), dim3((unsigned)nblocks), dim3(TX * TY), 0, s, cases,
-                       first, ncases);
-  else
-    hipLaunchKernelGGL((batch_step_kernel<T, TX, TY, false>), dim3((unsigned)nblocks), dim3(TX * TY), 0, s, cases,
-                       first, ncases);
-  return hipGetLastError();
+  return lat ? launch_batch_lat<T, TX, TY, true>(cases, first, ncases, nblocks, init, s)
+             : launch_batch_lat<T, TX, TY, false>(cases, first, ncases, nblocks, init, s);
 }
 
 template <typename T>
 hipError_t launch_batch_T(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int tx, int ty,
-                          hipStream_t s) {
-  if (tx == 32 && ty == 4) return launch_batch_tile<T, 32, 4>(cases, first, ncases, nblocks, init, s);
-  if (tx == 32 && ty == 8) return launch_batch_tile<T, 32, 8>(cases, first, ncases, nblocks, init, s);
-  if (tx == 64 && ty == 4) return launch_batch_tile<T, 64, 4>(cases, first, ncases, nblocks, init, s);
-  if (tx == 64 && ty == 8) return launch_batch_tile<T, 64, 8>(cases, first, ncases, nblocks, init, s);
-  if (tx == 32 && ty == 16) return launch_batch_tile<T, 32, 16>(cases, first, ncases, nblocks, init, s);
+                          bool lat, hipStream_t s) {
+  if (tx == 32 && ty == 4) return launch_batch_tile<T, 32, 4>(cases, first, ncases, nblocks, init, lat, s);
+  if (tx == 32 && ty == 8) return launch_batch_tile<T, 32, 8>(cases, first, ncases, nblocks, init, lat, s);
+  if (tx == 64 && ty == 4) return launch_batch_tile<T, 64, 4>(cases, first, ncases, nblocks, init, lat, s);
+  if (tx == 64 && ty == 8) return launch_batch_tile<T, 64, 8>(cases, first, ncases, nblocks, init, lat, s);
+  if (tx == 32 && ty == 16) return launch_batch_tile<T, 32, 16>(cases, first, ncases, nblocks, init, lat, s);
   return hipErrorInvalidValue;
 }
 
 template <typename T, int TX, int TY>
 int resident_tile(int device) {
   int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)step_kernel<T, TX, TY, false>, TX * TY, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)step_kernel<T, TX, TY, false, false>, TX * TY, 0) !=
       hipSuccess)
     return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
@@ -623,7 +678,7 @@ int step_resident_blocks_T(int tx, int ty, int device) {
 
 #define LBM_INSTANTIATE_STEP(T)                                                 \
   template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t); \
-  template hipError_t launch_batch_T<T>(const StepArgs*, const int*, int, int, bool, int, int, hipStream_t); \
+  template hipError_t launch_batch_T<T>(const StepArgs*, const int*, int, int, bool, int, int, bool, hipStream_t); \
   template hipError_t launch_inflow_T<T>(const StepArgs&, hipStream_t);                                         \
   template hipError_t launch_batch_inflow_T<T>(const StepArgs*, const int*, int, int, long long, hipStream_t);          \
   template int step_resident_blocks_T<T>(int, int, int);

@@ -109,6 +109,8 @@ def library():
         L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int]
         L.lbm_batch_step.argtypes = [vp, ctypes.c_int]
         L.lbm_batch_sync.argtypes = [vp]
+        L.lbm_batch_unstable_cases.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.lbm_batch_unstable_cases.restype = ctypes.c_int
         L.lbm_batch_last_step_ms.argtypes = [vp]
         L.lbm_batch_last_step_ms.restype = ctypes.c_double
         L.lbm_batch_last_error.argtypes = [vp]
@@ -344,6 +346,15 @@ class Batch:
 
     def last_step_ms(self) -> float:
         return float(library().lbm_batch_last_step_ms(self.handle))
+
+    def unstable_cases(self) -> list:
+        """Indices of the cases the step kernel has flagged as unstable; they are no longer
+        stepped (lbm_batch_unstable_cases)."""
+        flags = (ctypes.c_int * len(self.cases))()
+        n = library().lbm_batch_unstable_cases(self.handle, flags)
+        if n < 0:
+            self._check(LBM_EDEVICE)
+        return [k for k in range(len(self.cases)) if flags[k]]
 
     @property
     def ncells(self) -> int:

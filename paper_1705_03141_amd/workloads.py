@@ -243,12 +243,13 @@ def rayleigh_taylor(width: int = 128, height: Optional[int] = None, atwood: floa
 def jet(nx: int = 256, ny: int = 256, nz: int = 1024, diameter: float = 16.0, u_in: float = 0.04,
         gamma: float = 1.6, nu_c: float = 1.8e-4, eta: float = 1.0, weber: float = 220.0, froude: float = 8.5,
         A: Optional[float] = None, beta: float = 0.7, noise_rel: float = 0.01, seed: int = 3,
-        steps: int = 30000, fields: bool = True) -> Problem:
+        steps: int = 30000, fields: bool = True, lateral: int = PERIODIC) -> Problem:
     """Liquid jet into an immiscible liquid (Sec. IV A): inflow disk on z = 0 with
-    free-slip elsewhere on that plane, convective outflow on the last plane, periodic
-    sides.  rho_j = 1; sigma from We = rho_j u^2 D / sigma; g from Fr = u^2 / (g D);
-    nu_j = eta nu_c.  ``A`` defaults to the surface-tension parameter that gives sigma at
-    the relaxation time of the continuous phase, sigma = (4/9) A (3 nu + 1/2)."""
+    free-slip elsewhere on that plane, convective outflow on the last plane, and sides that
+    are periodic or, with ``lateral=FREESLIP``, the free-slip walls of the paper's set-up.
+    rho_j = 1; sigma from We = rho_j u^2 D / sigma; g from Fr = u^2 / (g D); nu_j = eta nu_c.
+    ``A`` defaults to the surface-tension parameter that gives sigma at the relaxation time of
+    the continuous phase, sigma = (4/9) A (3 nu + 1/2)."""
     rho_r0 = 1.0
     rho_b0 = rho_r0 / gamma
     nu_j = eta * nu_c
@@ -262,7 +263,7 @@ def jet(nx: int = 256, ny: int = 256, nz: int = 1024, diameter: float = 16.0, u_
         return np.zeros(shape), np.full(shape, rho_b0), np.zeros((3,) + shape)
 
     pb = Problem(name="jet", nx=nx, ny=ny, nz=nz, rho_r0=rho_r0, rho_b0=rho_b0, nu_r=nu_j, nu_b=nu_c, A=A,
-                 beta=beta, faces=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, FREESLIP, OUTFLOW), force_model=1,
+                 beta=beta, faces=(lateral,) * 4 + (FREESLIP, OUTFLOW), force_model=1,
                  g=(0.0, 0.0, g), rho_ref=rho_b0, inflow=True, xc=(nx - 1) / 2.0, yc=(ny - 1) / 2.0,
                  diameter=diameter, u_in=u_in, noise_rel=noise_rel, seed=seed, steps=steps,
                  field_fn=make_fields)
@@ -336,17 +337,17 @@ PAPER_JETS = {
 }
 
 
-def paper_jet(case: str = "ref", fields: bool = True) -> Problem:
+def paper_jet(case: str = "ref", fields: bool = True, lateral: int = FREESLIP) -> Problem:
     """One of the paper's jets at its own size (Sec. IV B-C): "ref" (200 x 200 x 500, sinuous
     breakup, Regime II), "case1" (120 x 120 x 300, varicose, Regime I) or "case2"
-    (240 x 240 x 600, atomisation, Regime III).  No inflow noise: the paper adds no
-    perturbation, the instability grows from the flow itself.  A is set from sigma at the
-    continuous phase's relaxation time."""
+    (240 x 240 x 600, atomisation, Regime III), with the paper's free-slip lateral walls
+    (Sec. IV A).  No inflow noise: the paper adds no perturbation, the instability grows from
+    the flow itself.  A is set from sigma at the continuous phase's relaxation time."""
     c = PAPER_JETS[case]
     D, u = c["D"], c["u"]
     pb = jet(nx=8 * D, ny=8 * D, nz=20 * D, diameter=float(D), u_in=u, gamma=1.0 / c["rho_c"], nu_c=c["nu_c"],
              eta=c["nu_j"] / c["nu_c"], weber=u * u * D / c["sigma"], froude=u * u / (c["g"] * D), noise_rel=0.0,
-             fields=fields)
+             fields=fields, lateral=lateral)
     pb.name = f"paper_jet_{case}_{8 * D}x{8 * D}x{20 * D}"
     pb.t_unit = D / u  # steps per unit of t* = t u / D
     return pb
@@ -386,7 +387,8 @@ def small_configs():
     viscosity where they are stable, a reduced Rayleigh-Taylor box and a reduced jet with
     the physics of the full-size workloads; and, for the local viscosity and the
     density-ratio terms, the reduced jet at the paper's viscosity ratio eta = 4.2 (Table III),
-    a droplet with eta = 10 (nu_b = 1e-3) and one with density ratio gamma = 10."""
+    a droplet with eta = 10 (nu_b = 1e-3), one with density ratio gamma = 10, and the reduced
+    jet at eta = 4.2 between the free-slip lateral walls of the paper's jet set-up."""
     suga_drop = static_droplet(n=24, radius=6.0, rho_r0=1.5, rho_b0=1.0, nu=1.667e-2, A=0.01, beta=0.7)
     suga_drop.name = "droplet24_suga"
     eta_drop = static_droplet(n=24, radius=6.0, rho_r0=1.5, rho_b0=1.0, nu=1e-2, nu_b=1e-3, A=0.01, beta=0.7)
@@ -395,6 +397,8 @@ def small_configs():
     gamma_drop.name = "droplet24_gamma10"
     jet_eta = jet(nx=24, ny=24, nz=48, diameter=8.0, eta=4.2)
     jet_eta.name = "jet_small_eta4.2"
+    jet_walls = jet(nx=24, ny=24, nz=48, diameter=8.0, eta=4.2, lateral=FREESLIP)
+    jet_walls.name = "jet_small_walls"
     return {
         "droplet32": cfg_static_droplet(),
         "droplet24_suga": suga_drop,
@@ -403,4 +407,5 @@ def small_configs():
         "droplet24_eta10": eta_drop,
         "droplet24_gamma10": gamma_drop,
         "jet_small_eta": jet_eta,
+        "jet_small_walls": jet_walls,
     }

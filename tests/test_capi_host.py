@@ -55,11 +55,13 @@ def test_parameter_validation(L):
     _expect(lbm.LBM_EINVAL, pb, nx=19884108, ny=1, nz=3)
     # gamma < 19/27 gives alpha_r < 0
     _expect(lbm.LBM_EINVAL, pb, rho_r0=0.5, rho_b0=1.0)
-    # x faces must be periodic; z faces paired
-    p = lbm.params_from_problem(pb)
-    p.face[0] = W.BOUNCEBACK
+    # x and y faces: both periodic or both free-slip (lateral walls); z faces paired
     ctx = ctypes.c_void_p()
-    assert L.lbm_create(ctypes.byref(p), None, ctypes.byref(ctx)) == lbm.LBM_EINVAL
+    for faces in ((W.BOUNCEBACK, W.BOUNCEBACK), (W.FREESLIP, W.PERIODIC), (W.OUTFLOW, W.OUTFLOW)):
+        for d in (0, 1):
+            p = lbm.params_from_problem(pb)
+            p.face[2 * d], p.face[2 * d + 1] = faces
+            assert L.lbm_create(ctypes.byref(p), None, ctypes.byref(ctx)) == lbm.LBM_EINVAL, (d, faces)
     p = lbm.params_from_problem(pb)
     p.face[4] = W.BOUNCEBACK
     assert L.lbm_create(ctypes.byref(p), None, ctypes.byref(ctx)) == lbm.LBM_EINVAL
@@ -84,6 +86,8 @@ def test_create_without_gpu_reports_device_error(L):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     _expect(lbm.LBM_EDEVICE, W.cfg_static_droplet())
+    # free-slip lateral walls pass validation
+    _expect(lbm.LBM_EDEVICE, W.jet(nx=24, ny=24, nz=48, diameter=8.0, lateral=W.FREESLIP))
     # the largest plane passes validation (and only then meets the missing device)
     _expect(lbm.LBM_EDEVICE, W.cfg_static_droplet(), nx=19884107, ny=1, nz=3)
 

@@ -91,7 +91,7 @@ U_TOL = {"droplet24_gamma10": 5.6e-5, "droplet24_suga": 2.4e-5}
 @pytest.mark.parametrize("name,steps", [("droplet32", (200, 1000)), ("droplet24_suga", (300, 1000)),
                                         ("rt_small", (300, 1000)), ("jet_small", (300, 1000)),
                                         ("jet_small_eta", (300, 1000)), ("droplet24_eta10", (300, 1000)),
-                                        ("droplet24_gamma10", (300, 1000))])
+                                        ("droplet24_gamma10", (300, 1000)), ("jet_small_walls", (300, 1000))])
 def test_parity_fields(O, name, steps):
     pb = W.small_configs()[name]
     log(f"[parity] {name} {pb.nx}x{pb.ny}x{pb.nz} steps {steps}")
@@ -147,6 +147,29 @@ def test_tilings_ragged_domain(O, tiling):
     got = lat.populations()
     same = bool(np.array_equal(got, ref_lat.populations()))
     assert same, "tilings disagree"
+    ref = o.populations()
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    log(f"  max population error {err:.3e}")
+    assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("tiling", [(32, 4, 5), (64, 4, 7), (32, 8, 64)])
+def test_tilings_free_slip_box(O, tiling):
+    """A 37 x 29 x 23 box with free-slip walls on all six faces (reading R9 on every axis,
+    edges and corners included) and a droplet pressed against the -x, -y corner: all tilings
+    agree bit for bit and with the oracle."""
+    pb = W.static_droplet(dims=(37, 29, 23), radius=6.0, rho_r0=1.5, rho_b0=1.0, nu=0.05, A=0.01,
+                          center=(4.0, 5.5, 11.0))
+    pb.faces = (W.FREESLIP,) * 6
+    log(f"[free-slip box] {tiling} 37x29x23")
+    lat = lbm.Lattice(pb, tiling=tiling)
+    ref_lat = lbm.Lattice(pb, tiling=(32, 8, 16))
+    o = O.Oracle(pb)
+    lat.step(40)
+    ref_lat.step(40)
+    o.step(40)
+    got = lat.populations()
+    assert bool(np.array_equal(got, ref_lat.populations())), "tilings disagree"
     ref = o.populations()
     err = float(np.abs(got - ref).max() / np.abs(ref).max())
     log(f"  max population error {err:.3e}")
