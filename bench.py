@@ -1,18 +1,22 @@
 """Benchmark of the D3Q27 colour-fluid step on one MI355X.
 
-Workload: the Rayleigh-Taylor problem on 128 x 128 x 512 (At = 0.5, g = 1e-5, Re = 256,
-seeded single-mode interface), the configuration the throughput metric is quoted on; FP32
+Workload (default): the liquid jet on 256 x 256 x 1024 (D = 16 inflow disk with 1 % noise,
+u = 0.04, gamma 1.6, nu 1.8e-4, We 220, Fr 8.5, free-slip inlet plane, convective outflow,
+periodic sides), the largest single-GPU configuration the throughput metric is quoted on;
+``--workload rt`` runs the Rayleigh-Taylor problem on 128 x 128 x 512 instead.  FP32
 populations and arithmetic.  A "step" is one full time step of the method over the whole
-lattice.  Prints one JSON line:
+lattice (outlet plane, fused step kernel, inflow plane).  Prints one JSON line:
 
   value       MLUPS = cells x steps / wall time of the timed steps (inputs resident in HBM)
   roofline    the step kernel against HBM: achieved = 432 B per cell update (one read and one
-              write of 2 x 27 FP32 populations, the standard two-colour traffic) x cells /
-              mean kernel time from HIP events on the library's stream; peak 8000 GB/s
+              write of 2 x 27 FP32 populations, the standard two-colour traffic of the
+              method) x cells / mean kernel time from HIP events on the library's stream;
+              peak 8000 GB/s.  The kernel itself keeps a 32-value state and moves 256 B per
+              update; extra.measured_hbm_gbs is what the HBM counters saw over the same time.
   traffic     HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
               (null when the kernel sources differ from those the counters were taken on)
-  cpu_baseline  the FP64 oracle timed on the host cores on a 128 x 128 x 64 window of the
-              same workload (rank 0, N = 1 only)
+  cpu_baseline  the FP64 oracle timed on the host cores on a window of the same workload
+              (rank 0, N = 1 only)
 
 Also reported (extra): the FP16- and BF16-storage throughput, the bytes the kernel itself
 must move per update (27 stored deviations + 5 FP32 scalars, read and written once) and
@@ -32,11 +36,9 @@ sys.path.insert(0, HERE)
 
 PEAK_GBS = 8000.0
 # HBM bytes per step-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
-# scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000); valid
-# only for the kernel sources they were taken on.
-COUNTERS = {"sources_sha16": "19551849d330d7d8", "storage": "f32", "fetch_kib": 557888.9, "fetch_scale": 2.0,
-            "write_kib": 1048576.0, "write_scale": 1.0, "tile": [64, 4],
-            "workload": "rayleigh_taylor_128x128x512"}
+# scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000), per
+# workload; valid only for the kernel sources and tile shape they were taken on.
+COUNTERS = {}
 KERNEL_SOURCES = ["csrc/lbm_cell.h", "csrc/lbm_device.h", "csrc/lbm_kernels.h", "csrc/lbm_kernels_impl.h",
                   "csrc/lbm_step.h", "csrc/lbm_storage_f32.hip", "build.py"]
 STD_BYTES = 432.0  # 2 colours x 27 populations x 4 B, read + write
@@ -79,12 +81,12 @@ def kernel_sources_sha16() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str, tile, workload: str = "rayleigh_taylor_128x128x512"):
-    """HBM bytes per launch, or None when the counters were taken on other kernel sources,
-    another tile shape or another workload."""
-    c = COUNTERS
-    if (storage != c["storage"] or kernel_sources_sha16() != c["sources_sha16"] or list(tile[:2]) != c["tile"]
-            or workload != c["workload"]):
+def measured_traffic(storage: str, tile, workload: str):
+    """HBM bytes per launch, or None when no counters were taken on this workload, or they were
+    taken on other kernel sources, another storage or another tile shape."""
+    c = COUNTERS.get(workload)
+    if (c is None or storage != c["storage"] or kernel_sources_sha16() != c["sources_sha16"]
+            or list(tile[:2]) != c["tile"]):
         return None
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
@@ -94,19 +96,25 @@ def log(msg):
 
 
 def cpu_baseline(pb_full, steps=150):
+    """The FP64 oracle on a window of the workload: the jet's first 16 planes (inflow disk and
+    free-slip inlet plane, about 1 M cells), or the 64 planes around the Rayleigh-Taylor
+    interface."""
     import numpy as np  # noqa: F401
     import oracle
 
-    win = pb_full.window(0, 0, pb_full.nz // 2 - 32, pb_full.nx, pb_full.ny, 64)
+    if pb_full.inflow:
+        win = pb_full.window(0, 0, 0, pb_full.nx, pb_full.ny, 16)
+    else:
+        win = pb_full.window(0, 0, pb_full.nz // 2 - 32, pb_full.nx, pb_full.ny, 64)
     o = oracle.Oracle(win)
     o.step(1)  # first touch
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    where = "at the inflow end" if pb_full.inflow else "around the interface"
     return {"value": win.ncells * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{win.nx}x{win.ny}x{win.nz} window of the same workload around the interface, {steps} steps, "
-                      f"{dt:.1f} s"}
+            "sample": f"{win.nx}x{win.ny}x{win.nz} window of the same workload {where}, {steps} steps, {dt:.1f} s"}
 
 
 def copy_calibration(nbytes=1 << 30, reps=5):
@@ -146,11 +154,23 @@ def sweep(steps: int, warmup: int, storage: str = "f16"):
     b.step(warmup)
     b.sync()
     torch.cuda.synchronize()
+    # long runs go in chunks of 500 steps, after each of which the step the cases the kernel
+    # flagged as unstable were found at is noted (a flagged case is no longer stepped)
+    found = {}
     t0 = time.perf_counter()
-    b.step(steps)
+    done = 0
+    while done < steps:
+        k = min(500, steps - done) if steps > 1000 else steps
+        b.step(k)
+        done += k
+        for c in b.unstable_cases():
+            found.setdefault(c, warmup + done)
+        if steps > 1000:
+            log(f"sweep: {done}/{steps} steps, {len(found)} unstable")
     b.sync()
     wall = time.perf_counter() - t0
-    unstable = [k for k, c in enumerate(b.cases) if c.diagnostics()["unstable"]]
+    unstable = [{"case": k, "name": cases[k].name, "regime": cases[k].regime, "found_by_step": s}
+                for k, s in sorted(found.items())]
     mlups = ncells * steps / wall / 1e6
     std_bytes = 432.0 if storage == "f32" else 216.0
     achieved = std_bytes * ncells / (b.last_step_ms() * 1e-3) / 1e9
@@ -288,8 +308,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--workload", default="rt", choices=["rt", "jet"],
-                    help="rt: Rayleigh-Taylor 128 x 128 x 512 (the default); jet: 256 x 256 x 1024")
+    ap.add_argument("--workload", default="jet", choices=["rt", "jet"],
+                    help="jet: the liquid jet 256 x 256 x 1024 (the default); rt: Rayleigh-Taylor 128 x 128 x 512")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first (lbm_autotune) instead of using the default 64 x 4")
@@ -365,7 +385,9 @@ def main():
         "config": {"workload": pb.name, "nx": pb.nx, "ny": pb.ny, "nz": pb.nz, "storage": args.storage,
                    "tile": list(diag["tiling"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_GBS, "traffic": traffic},
+                     "frac": achieved / PEAK_GBS, "traffic": traffic,
+                     "basis": "432 B per cell update (2 x 27 FP32 populations read and written) x cells / "
+                              "mean step-kernel time"},
         "extra": extra,
     }
     if not args.no_cpu_baseline:

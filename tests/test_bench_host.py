@@ -21,22 +21,23 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_only_for_the_profiled_configuration(monkeypatch):
-    c = dict(bench.COUNTERS)
-    c["sources_sha16"] = bench.kernel_sources_sha16()
-    monkeypatch.setattr(bench, "COUNTERS", c)
-    t = bench.measured_traffic("f32", [64, 4, 64])
-    assert t == pytest.approx((c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0)
-    assert bench.measured_traffic("f16", [64, 4, 64]) is None
-    assert bench.measured_traffic("f32", [32, 8, 64]) is None
+    entry = {"sources_sha16": bench.kernel_sources_sha16(), "storage": "f32", "fetch_kib": 1.0e6, "fetch_scale": 2.0,
+             "write_kib": 2.0e6, "write_scale": 1.0, "tile": [64, 4]}
+    monkeypatch.setattr(bench, "COUNTERS", {"jet_256x256x1024": entry})
+    t = bench.measured_traffic("f32", [64, 4, 64], "jet_256x256x1024")
+    assert t == pytest.approx((1.0e6 * 2.0 + 2.0e6) * 1024.0)
+    assert bench.measured_traffic("f16", [64, 4, 64], "jet_256x256x1024") is None
+    assert bench.measured_traffic("f32", [32, 8, 64], "jet_256x256x1024") is None
+    assert bench.measured_traffic("f32", [64, 4, 64], "rayleigh_taylor_128x128x512") is None
+    entry["sources_sha16"] = "0" * 16
     assert bench.measured_traffic("f32", [64, 4, 64], "jet_256x256x1024") is None
-    c["sources_sha16"] = "0" * 16
-    assert bench.measured_traffic("f32", [64, 4, 64]) is None
 
 
 def test_counters_are_plausible_for_the_state():
-    """The stored counters describe one FP32 step of the 128x128x512 workload: writes are the
-    128-byte state of every cell, reads at least that."""
-    c = bench.COUNTERS
-    cells = 128 * 128 * 512
-    assert c["write_kib"] * c["write_scale"] * 1024 == pytest.approx(128 * cells, rel=0.01)
-    assert c["fetch_kib"] * c["fetch_scale"] * 1024 >= 128 * cells
+    """Stored counters describe one FP32 step of their workload: writes are the 128-byte state
+    of every cell, reads at least that."""
+    cells = {"jet_256x256x1024": 256 * 256 * 1024, "rayleigh_taylor_128x128x512": 128 * 128 * 512}
+    for name, c in bench.COUNTERS.items():
+        n = cells[name]
+        assert c["write_kib"] * c["write_scale"] * 1024 == pytest.approx(128 * n, rel=0.01), name
+        assert c["fetch_kib"] * c["fetch_scale"] * 1024 >= 128 * n, name
