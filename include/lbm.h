@@ -145,6 +145,17 @@ lbm_status lbm_read_field(lbm_ctx *ctx, int field, double *dst);
  * the state (see lbm_sync). */
 lbm_status lbm_read_field_box(lbm_ctx *ctx, int field, int x0, int y0, int z0, int wx, int wy, int wz, double *dst);
 
+/* The same read-back for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): lbm_read_field_box without any
+ * hipMalloc or hipFree.  The FP64 staging of the fields kernel is a fixed 8 MiB array per
+ * device (2^20 doubles, held until the process ends; its address is taken in lbm_create)
+ * instead of a buffer the context allocates on demand.  The box is read in z slices of at
+ * most 2^20 / 7 cells; a box with wx*wy > 149796 is rejected with LBM_EINVAL.  All contexts
+ * on one device share the array: calls that overlap on one device race.  Other arguments,
+ * results and errors as lbm_read_field_box. */
+lbm_status lbm_read_field_box_noalloc(lbm_ctx *ctx, int field, int x0, int y0, int z0, int wx, int wy, int wz,
+                                      double *dst);
+
 /* Pre-collision populations of the current time, per colour: dst holds 2*27*ncells
  * doubles ordered [colour (0 red, 1 blue)][velocity][cell]. */
 lbm_status lbm_read_populations(lbm_ctx *ctx, double *dst);

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,7 @@ struct lbm_ctx {
   double* diag_part = nullptr;
   double* diag_out = nullptr;
   int* unstable = nullptr;  // device flag the step kernel sets on a NaN / non-positive density
+  int device = 0;           // the device current at lbm_create
   long long diag_blocks = 0;
   int cur = 0;              // index of the state holding the current time
   int out_cur = 0;          // index of the outlet record of the latest time
@@ -67,6 +69,33 @@ static lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 static const double kAlphaB = 8.0 / 27.0;
+
+// ---------------------------------------------------------------- no-allocation staging
+// lbm_read_field_box_noalloc stages the FP64 fields of one z slice of the box in this
+// file-scope array instead of a buffer the context allocates: 2^20 doubles (8 MiB) per
+// device, held until the process ends.  The fields kernel writes 7 values per cell, so a slice
+// holds at most kScratchDoubles / 7 cells.  Host code must not pass the array's name to a
+// kernel: each device's address comes from hipGetSymbolAddress, taken once per device in
+// lbm_create with that device current, and is used everywhere instead.  Every call on a
+// device shares its array; calls that overlap on one device race.
+constexpr size_t kScratchDoubles = size_t(1) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static double* g_scratch_ptr[kScratchDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Address of this device's scratch array (set up on the first call for the device; the
+// device must be current).  nullptr if the lookup failed.
+static double* scratch_on(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    double* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
 
 // Validation of lbm_params; fills the derived constants.
 static lbm_status check_params(const lbm_params* p, lbm_ctx* c, std::string& msg) {
@@ -176,6 +205,10 @@ extern "C" lbm_status lbm_create(const lbm_params* params, void* hip_stream, lbm
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
     delete c;
     return fail(nullptr, LBM_EDEVICE, "no HIP device");
+  }
+  if (hipGetDevice(&c->device) != hipSuccess || !scratch_on(c->device)) {
+    delete c;
+    return fail(nullptr, LBM_EDEVICE, "no device address for the staging array");
   }
   const size_t n = (size_t)c->geo.n, plane = (size_t)c->geo.plane;
   bool ok = true;
@@ -447,6 +480,34 @@ extern "C" lbm_status lbm_read_field_box(lbm_ctx* c, int field, int x0, int y0, 
     LBM_HIP(c, hipStreamSynchronize(c->stream));
   }
   (void)nb;
+  return check_unstable(c);
+}
+
+extern "C" lbm_status lbm_read_field_box_noalloc(lbm_ctx* c, int field, int x0, int y0, int z0, int wx, int wy,
+                                                 int wz, double* dst) {
+  if (!c || !dst) return LBM_EINVAL;
+  if (!c->initialised) return fail(c, LBM_ESTATE, "read before lbm_init_fields");
+  if (field < 0 || field > 6) return fail(c, LBM_EINVAL, "unknown field");
+  const Geo& G = c->geo;
+  if (x0 < 0 || y0 < 0 || z0 < 0 || wx < 1 || wy < 1 || wz < 1 || x0 + wx > G.nx || y0 + wy > G.ny || z0 + wz > G.nz)
+    return fail(c, LBM_EINVAL, "box outside the lattice");
+  const size_t slice = (size_t)wx * wy;
+  if (slice * 7 > kScratchDoubles)
+    return fail(c, LBM_EINVAL, "box too wide for the no-allocation staging: wx*wy must be at most " +
+                                   std::to_string(kScratchDoubles / 7));
+  double* stage = g_scratch_ptr[c->device];  // set up by lbm_create on this device
+  if (!stage) return fail(c, LBM_EDEVICE, "no staging array on this device");
+  const int zs = (int)std::min<size_t>((size_t)wz, kScratchDoubles / (slice * 7));
+  AuxArgs a = aux_args(c);
+  for (int z = 0; z < wz; z += zs) {
+    const int h = std::min(zs, wz - z);
+    const size_t ns = slice * h;
+    hipError_t e = launch_fields((int)c->p.storage, a, x0, y0, z0 + z, wx, wy, h, stage, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fields kernel");
+    LBM_HIP(c, hipMemcpyAsync(dst + (size_t)z * slice, stage + (size_t)field * ns, ns * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(c, hipStreamSynchronize(c->stream));
+  }
   return check_unstable(c);
 }
 

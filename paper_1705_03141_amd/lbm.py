@@ -86,6 +86,8 @@ def library():
         L.lbm_step_count.restype = ctypes.c_longlong
         L.lbm_read_field.argtypes = [vp, ctypes.c_int, _D]
         L.lbm_read_field_box.argtypes = [vp, ctypes.c_int] + [ctypes.c_int] * 6 + [_D]
+        L.lbm_read_field_box_noalloc.argtypes = [vp, ctypes.c_int] + [ctypes.c_int] * 6 + [_D]
+        L.lbm_read_field_box_noalloc.restype = ctypes.c_int
         L.lbm_read_populations.argtypes = [vp, _D]
         L.lbm_state_bytes.argtypes = [vp]
         L.lbm_state_bytes.restype = ctypes.c_size_t
@@ -277,6 +279,14 @@ class Lattice:
         rr, rb = self.field("rho_r"), self.field("rho_b")
         u = np.stack([self.field("ux"), self.field("uy"), self.field("uz")])
         return {"rho_r": rr, "rho_b": rb, "u": u, "rho": rr + rb, "phi": self.field("phi"), "p": self.field("p")}
+
+    def field_box_noalloc(self, name: str, x0, y0, z0, wx, wy, wz) -> np.ndarray:
+        """field_box through the entry point that allocates no device memory
+        (lbm_read_field_box_noalloc)."""
+        out = np.empty(wx * wy * wz)
+        _check(self.ctx, library().lbm_read_field_box_noalloc(self.ctx, FIELDS[name], x0, y0, z0, wx, wy, wz,
+                                                              _ptr(out)))
+        return out.reshape((wz, wy, wx))
 
     def populations(self) -> np.ndarray:
         out = np.empty(2 * Q * self.n)
