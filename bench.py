@@ -148,7 +148,7 @@ def sweep(steps: int, warmup: int, storage: str = "f16"):
     cases = W.regime_sweep()
     ncells = sum(c.ncells for c in cases)
     log(f"sweep: {len(cases)} cases, {ncells / 1e6:.0f} M cells, storage {storage}")
-    b = lbm.Batch(cases, storage=storage)
+    b = lbm.Batch(cases, storage=storage, progress=lambda m: log(f"sweep: {m}"))
     log("sweep: initialised; autotuning")
     b.autotune(trial_steps=5)
     b.step(warmup)
@@ -256,6 +256,74 @@ def surrogate_bench(steps: int, warmup: int):
                       "dtype": "bf16 MFMA, f32 accumulate"}), flush=True)
 
 
+def surrogate_sweep(steps: int, train_steps: int = 1500, start: int = 5, ahead: int = 10):
+    """The surrogate in the 64-case regime-map sweep (FP16 storage): the lattice runs every
+    case for `steps` steps and keeps the 4x-coarsened (phi, u/u_in) every 200 steps in a
+    64 x 64 x 256 x 4 box; a 3-member ensemble trains on 48 cases; the other 16 are
+    fast-forwarded from snapshot `start` for up to `ahead` horizons while the ensemble's
+    predicted interface error stays within one coarse cell, and every accepted prediction is
+    scored against plain FP32 lattice runs of those cases.  Reports the surrogate's share of
+    the horizons, its interface error against FP32 (and that of the FP16 lattice itself for
+    context) and the lattice time it saves."""
+    import numpy as np
+    import torch
+    from paper_1705_03141_amd import metrics
+    from paper_1705_03141_amd import surrogate as S
+    from paper_1705_03141_amd import workloads as W
+
+    horizon = 200
+    snaps = steps // horizon
+    cases = W.regime_sweep()
+    held = cases[48:]
+    log(f"surrogate sweep: {len(cases)} cases, {snaps} snapshots of {horizon} steps (FP16 lattice)")
+    states, t16, unstable = S.coarse_trajectories(cases, horizon, snaps, storage="f16",
+                                                  progress=lambda m: log(f"surrogate sweep: FP16 lattice: {m}"))
+    log(f"surrogate sweep: FP16 lattice {t16:.1f} s; FP32 lattice of the 16 held-out cases")
+    truth, t32, _ = S.coarse_trajectories(held, horizon, snaps, storage="f32",
+                                          progress=lambda m: log(f"surrogate sweep: FP32 lattice: {m}"))
+    train = [k for k in range(48) if k not in unstable]
+    ens = S.Ensemble(batch=4, members=3, seed=0)
+    t0 = time.perf_counter()
+    losses = ens.train(states, cases=train, steps=train_steps)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"surrogate sweep: ensemble trained in {t_train:.1f} s, losses {losses}")
+    ext = [S.coarse_extent(pb) for pb in held]
+    rep = S.fast_forward(ens, states[:, 48:], truth, list(range(16)), ext, start=start, horizons=ahead)
+    cells = np.array([pb.ncells for pb in cases], dtype=float)
+    t_case = t16 / snaps * cells[48:] / cells.sum()
+    x = states[start, 48:49]
+    ens.predict(x)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(10):
+        ens.predict(x)
+    torch.cuda.synchronize()
+    t_pred = (time.perf_counter() - t1) / 10
+    acc = [a for r in rep.values() for a in r["actual"]]
+    taken = sum(r["taken"] for r in rep.values())
+    saved = sum(r["taken"] * (t_case[k] - t_pred) for k, r in rep.items())
+    lattice_total = float(t_case.sum()) * ahead
+    fp16_err = []
+    for k, (d, h, w) in enumerate(ext):
+        for s_ in range(start + 1, start + ahead + 1):
+            fp16_err.append(S.interface_error_coarse(states[s_, 48 + k, :d, :h, :w, 0].cpu().numpy(),
+                                                     truth[s_, k, :d, :h, :w, 0].cpu().numpy()))
+    print(json.dumps({
+        "metric": "surrogate fast-forward of the 64-case regime-map sweep",
+        "cases": {"train": len(train), "held_out": 16, "unstable": unstable},
+        "input": list(S.BOX) + [4], "horizon_steps": horizon, "snapshots": snaps, "start_step": start * horizon,
+        "horizons_by_surrogate": taken, "horizons_offered": 16 * ahead,
+        "interface_error_vs_fp32_coarse_cells": {"mean": float(np.mean(acc)) if acc else None,
+                                                 "max": float(np.max(acc)) if acc else None},
+        "fp16_lattice_interface_error_vs_fp32_coarse_cells": {"mean": float(np.mean(fp16_err)),
+                                                              "max": float(np.max(fp16_err))},
+        "rejected": [{"case": k, **r["rejected"]} for k, r in rep.items() if r["rejected"]],
+        "ms_per_horizon": {"lattice_per_case_mean": float(t_case.mean() * 1e3), "ensemble_prediction": t_pred * 1e3},
+        "lattice_seconds_saved": saved, "lattice_seconds_of_the_window": lattice_total,
+        "train_seconds": t_train, "member_losses": losses}), flush=True)
+
+
 def interface_error(workload: str, steps: int):
     """Interface-position error of FP16 / BF16 storage against FP32 storage after `steps`
     steps (metrics.interface_position_error; lattice units).  The control "f32_perturbed" is
@@ -321,6 +389,9 @@ def main():
                     help="instead: time one GPU's z-slab (256 x 256 x 128) of the jet split over 8 GPUs")
     ap.add_argument("--surrogate", action="store_true",
                     help="instead: time training steps of the surrogate network on the 64 x 64 x 256 x 4 input")
+    ap.add_argument("--surrogate-sweep", action="store_true",
+                    help="instead: train the surrogate ensemble on the 64-case sweep's trajectories (--steps lattice "
+                         "steps) and fast-forward 16 held-out cases with it")
     ap.add_argument("--interface-error", choices=["rt", "jet"],
                     help="instead of timing: run the workload for --steps steps with FP32, FP16 and BF16 "
                          "storage and print the interface-position error of the half-precision runs")
@@ -341,6 +412,9 @@ def main():
         return
     if args.surrogate:
         surrogate_bench(args.steps, args.warmup)
+        return
+    if args.surrogate_sweep:
+        surrogate_sweep(args.steps)
         return
     if args.slab:
         slab_bench(args.steps, args.warmup)

@@ -156,6 +156,14 @@ lbm_status lbm_read_field_box(lbm_ctx *ctx, int field, int x0, int y0, int z0, i
 lbm_status lbm_read_field_box_noalloc(lbm_ctx *ctx, int field, int x0, int y0, int z0, int wx, int wy, int wz,
                                       double *dst);
 
+/* Coarse-grained state of the current time for the learned surrogate: over every block of
+ * factor^3 cells, the means of phi and of u / u_scale (FP32), written to DEVICE memory dst as
+ * [cz][cy][cx][4] inside a padded box of pd x ph x pw voxels (entries outside the coarse
+ * lattice are not written; dst 16-byte aligned).  Enqueued on the context's stream (no
+ * synchronisation).  LBM_EINVAL unless factor divides nx, ny and nz, the coarse lattice fits
+ * the box and u_scale > 0. */
+lbm_status lbm_coarse_state(lbm_ctx *ctx, int factor, double u_scale, float *dst, int pd, int ph, int pw);
+
 /* Pre-collision populations of the current time, per colour: dst holds 2*27*ncells
  * doubles ordered [colour (0 red, 1 blue)][velocity][cell]. */
 lbm_status lbm_read_populations(lbm_ctx *ctx, double *dst);

@@ -511,6 +511,22 @@ extern "C" lbm_status lbm_read_field_box_noalloc(lbm_ctx* c, int field, int x0, 
   return check_unstable(c);
 }
 
+extern "C" lbm_status lbm_coarse_state(lbm_ctx* c, int factor, double u_scale, float* dst, int pd, int ph, int pw) {
+  if (!c || !dst) return LBM_EINVAL;
+  if (!c->initialised) return fail(c, LBM_ESTATE, "read before lbm_init_fields");
+  const Geo& G = c->geo;
+  if (factor < 1 || G.nx % factor || G.ny % factor || G.nz % factor)
+    return fail(c, LBM_EINVAL, "the lattice sizes must be multiples of the coarsening factor");
+  if (!(u_scale > 0.0)) return fail(c, LBM_EINVAL, "u_scale must be > 0");
+  if (G.nz / factor > pd || G.ny / factor > ph || G.nx / factor > pw)
+    return fail(c, LBM_EINVAL, "the coarse state does not fit the padded box");
+  if (reinterpret_cast<uintptr_t>(dst) % 16) return fail(c, LBM_EINVAL, "dst must be 16-byte aligned");
+  AuxArgs a = aux_args(c);
+  hipError_t e = launch_coarse((int)c->p.storage, a, factor, (float)(1.0 / u_scale), dst, ph, pw, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "coarse kernel");
+  return LBM_OK;
+}
+
 extern "C" lbm_status lbm_read_field(lbm_ctx* c, int field, double* dst) {
   if (!c) return LBM_EINVAL;
   return lbm_read_field_box(c, field, 0, 0, 0, c->geo.nx, c->geo.ny, c->geo.nz, dst);

@@ -93,6 +93,15 @@ hipError_t launch_populations(int storage, const AuxArgs& a, double* out, hipStr
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_coarse(int storage, const AuxArgs& a, int f, float inv_u, float* out, int ph, int pw, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_coarse_T<float>(a, f, inv_u, out, ph, pw, s);
+    case 1: return launch_coarse_T<_Float16>(a, f, inv_u, out, ph, pw, s);
+    case 2: return launch_coarse_T<bf16>(a, f, inv_u, out, ph, pw, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_diag(int storage, const AuxArgs& a, const DiagQuery& q, double* part, long long nblocks,
                        double* out, hipStream_t s) {
   switch (storage) {

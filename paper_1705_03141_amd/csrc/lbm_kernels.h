@@ -80,6 +80,8 @@ hipError_t launch_fields_T(const AuxArgs& a, int x0, int y0, int z0, int wx, int
 template <typename T>
 hipError_t launch_populations_T(const AuxArgs& a, double* out, hipStream_t s);
 template <typename T>
+hipError_t launch_coarse_T(const AuxArgs& a, int f, float inv_u, float* out, int ph, int pw, hipStream_t s);
+template <typename T>
 hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, long long nblocks, double* out,
                          hipStream_t s);
 
@@ -107,6 +109,7 @@ hipError_t launch_batch_inflow(int storage, const StepArgs* cases, const int* fi
 hipError_t launch_fields(int storage, const AuxArgs& a, int x0, int y0, int z0, int wx, int wy, int wz, double* out,
                          hipStream_t s);
 hipError_t launch_populations(int storage, const AuxArgs& a, double* out, hipStream_t s);
+hipError_t launch_coarse(int storage, const AuxArgs& a, int f, float inv_u, float* out, int ph, int pw, hipStream_t s);
 hipError_t launch_diag(int storage, const AuxArgs& a, const DiagQuery& q, double* part, long long nblocks,
                        double* out, hipStream_t s);
 

@@ -473,6 +473,37 @@ __global__ void __launch_bounds__(256) fields_kernel(const AuxArgs A, int x0, in
   out[6 * nb + k] = rr * 9.0 * (1.0 - (double)A.pc.alpha_r) / 19.0 + rb * 9.0 * (1.0 - (double)A.pc.alpha_b) / 19.0;
 }
 
+// Coarse-grained state: (phi, ux/u_scale, uy/u_scale, uz/u_scale) averaged over f^3 blocks of
+// cells, written as FP32 into out[cz][cy][cx][4] of a padded box of pd x ph x pw voxels.
+template <typename T>
+__global__ void __launch_bounds__(256) coarse_kernel(const AuxArgs A, int f, float inv_u, float* __restrict__ out,
+                                                     int ph, int pw) {
+  const Geo& G = A.geo;
+  const int cx_n = G.nx / f, cy_n = G.ny / f, cz_n = G.nz / f;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)cx_n * cy_n * cz_n) return;
+  const int cx = (int)(k % cx_n), cy = (int)((k / cx_n) % cy_n), cz = (int)(k / ((long long)cx_n * cy_n));
+  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int dz = 0; dz < f; ++dz)
+    for (int dy = 0; dy < f; ++dy)
+      for (int dx = 0; dx < f; ++dx) {
+        const int x = cx * f + dx, y = cy * f + dy, z = cz * f + dz;
+        float rho, rho_r, rho_b, j[3], fr[Q], fb[Q];
+        cell_state<T>(A, x, y, z, rho, rho_r, rho_b, j, fr, fb, false);
+        float F[3];
+        body_force(A, rho, F);
+        if (is_inflow(G, x, y, z)) F[0] = F[1] = F[2] = 0.0f;
+        const float inv = 1.0f / rho;
+        s[0] += (rho_r - rho_b) * inv;
+        s[1] += (j[0] + 0.5f * F[0]) * inv * inv_u;
+        s[2] += (j[1] + 0.5f * F[1]) * inv * inv_u;
+        s[3] += (j[2] + 0.5f * F[2]) * inv * inv_u;
+      }
+  const float w = 1.0f / (float)(f * f * f);
+  float4* o = reinterpret_cast<float4*>(out) + ((long long)cz * ph + cy) * pw + cx;
+  *o = make_float4(s[0] * w, s[1] * w, s[2] * w, s[3] * w);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) populations_kernel(const AuxArgs A, double* __restrict__ out) {
   const Geo& G = A.geo;
@@ -588,6 +619,13 @@ hipError_t launch_fields_T(const AuxArgs& a, int x0, int y0, int z0, int wx, int
 }
 
 template <typename T>
+hipError_t launch_coarse_T(const AuxArgs& a, int f, float inv_u, float* out, int ph, int pw, hipStream_t s) {
+  const long long nb = (long long)(a.geo.nx / f) * (a.geo.ny / f) * (a.geo.nz / f);
+  hipLaunchKernelGGL(coarse_kernel<T>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, a, f, inv_u, out, ph, pw);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_populations_T(const AuxArgs& a, double* out, hipStream_t s) {
   hipLaunchKernelGGL(populations_kernel<T>, dim3((unsigned)((a.geo.n + 255) / 256)), dim3(256), 0, s, a, out);
   return hipGetLastError();
@@ -608,6 +646,7 @@ hipError_t launch_diag_T(const AuxArgs& a, const DiagQuery& q, double* part, lon
   template hipError_t launch_batch_outlet_T<T>(const AuxArgs*, const int*, int, int, long long, hipStream_t);                                            \
   template hipError_t launch_fields_T<T>(const AuxArgs&, int, int, int, int, int, int, double*, hipStream_t);    \
   template hipError_t launch_populations_T<T>(const AuxArgs&, double*, hipStream_t);                              \
+  template hipError_t launch_coarse_T<T>(const AuxArgs&, int, float, float*, int, int, hipStream_t);             \
   template hipError_t launch_diag_T<T>(const AuxArgs&, const DiagQuery&, double*, long long, double*, hipStream_t);
 
 }  // namespace lbm

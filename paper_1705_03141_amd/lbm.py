@@ -88,6 +88,8 @@ def library():
         L.lbm_read_field_box.argtypes = [vp, ctypes.c_int] + [ctypes.c_int] * 6 + [_D]
         L.lbm_read_field_box_noalloc.argtypes = [vp, ctypes.c_int] + [ctypes.c_int] * 6 + [_D]
         L.lbm_read_field_box_noalloc.restype = ctypes.c_int
+        L.lbm_coarse_state.argtypes = [vp, ctypes.c_int, ctypes.c_double, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.lbm_coarse_state.restype = ctypes.c_int
         L.lbm_read_populations.argtypes = [vp, _D]
         L.lbm_state_bytes.argtypes = [vp]
         L.lbm_state_bytes.restype = ctypes.c_size_t
@@ -288,6 +290,16 @@ class Lattice:
                                                               _ptr(out)))
         return out.reshape((wz, wy, wx))
 
+    def coarse_state_into(self, out, factor: int = 4, u_scale: float = 1.0):
+        """Write the factor^3 block means of (phi, u / u_scale) into the device tensor `out`
+        (FP32, shape (pd, ph, pw, 4) with the coarse lattice in its leading corner), on the
+        lattice's stream (lbm_coarse_state)."""
+        pd, ph, pw, c = out.shape
+        if c != 4 or not out.is_contiguous() or out.dtype.itemsize != 4:
+            raise ValueError("out must be a contiguous FP32 tensor of shape (pd, ph, pw, 4)")
+        _check(self.ctx, library().lbm_coarse_state(self.ctx, int(factor), float(u_scale),
+                                                    ctypes.c_void_p(out.data_ptr()), pd, ph, pw))
+
     def populations(self) -> np.ndarray:
         out = np.empty(2 * Q * self.n)
         _check(self.ctx, library().lbm_read_populations(self.ctx, _ptr(out)))
@@ -320,7 +332,8 @@ class Batch:
     all cases that share a storage type and tile shape.  ``cases[k]`` is a :class:`Lattice`
     view of case k (read-back, diagnostics); the batch owns the device memory."""
 
-    def __init__(self, problems, storage: str = "f32", stream: Optional[int] = None, init: bool = True):
+    def __init__(self, problems, storage: str = "f32", stream: Optional[int] = None, init: bool = True,
+                 progress=None):
         n = len(problems)
         arr = (lbm_params * n)(*[params_from_problem(pb, storage) for pb in problems])
         self.handle = ctypes.c_void_p()
@@ -339,6 +352,8 @@ class Batch:
                     lat.init_fields(rr, rb, None if not np.any(u) else u)
                     del rr, rb, u
             self.cases.append(lat)
+            if progress and (k + 1) % 8 == 0:
+                progress(f"{k + 1}/{n} cases initialised")
 
     def _check(self, status):
         if status != LBM_OK:

@@ -15,8 +15,11 @@ Architecture (channels-last, additive skips):
   y   = conv 32->32, channels 0..3 = change of (phi, ux, uy, uz)
 The input's channels 4..7 are zero (the convolution needs multiples of 8).
 
-The method stays the judge: `judge` runs the lattice over a calibration window and keeps
-the surrogate only where its interface error there is at most one coarse cell.
+Use in a regime-map sweep (`fast_forward`): an ensemble of independently initialised and
+trained networks advances each case by one horizon; the spread of the members' interface
+positions is the predicted interface error, known without running the lattice.  Where it
+exceeds one coarse cell the case falls back to the lattice.  The method stays the judge of
+what the surrogate delivers: its predictions are scored against the plain FP32 lattice.
 """
 from __future__ import annotations
 
@@ -313,10 +316,153 @@ def interface_error_coarse(phi_a: np.ndarray, phi_b: np.ndarray) -> float:
     return interface_position_error(phi_a, phi_b, periodic=(True, True, False))["mean_lu"]
 
 
-def judge(net: "Network", states_now: np.ndarray, states_next: np.ndarray, limit: float = 1.0):
-    """The method as judge: for each case, the surrogate's prediction of the next coarse state
-    against the lattice's own; cases whose interface moved by more than `limit` coarse cells
-    fall back to the lattice.  Returns (use_surrogate per case, interface error per case)."""
-    pred = net.predict(states_now)
-    errs = np.array([interface_error_coarse(pred[k, ..., 0], states_next[k, ..., 0]) for k in range(len(pred))])
-    return errs <= limit, errs
+
+# ---------------------------------------------------------------- surrogate in a sweep
+BOX = (256, 64, 64)  # padded coarse input (d, h, w) = (z, y, x): 4x-coarsened lattices up to 256 x 256 x 1024
+
+
+def coarse_trajectories(problems, horizon: int, snapshots: int, storage: str = "f16", box=BOX, factor: int = 4,
+                        progress=None):
+    """Coarse states (phi, u / u_in) of every problem every `horizon` steps, the problems
+    advanced together as one batch; kept on the GPU.  Returns (states, lattice seconds,
+    unstable cases): states is an FP32 tensor (snapshots + 1, ncases, d, h, w, 4) with each
+    case's coarse lattice in the leading corner of the d x h x w box and zeros beyond it.
+    `progress(text)`, if given, is called after the set-up and after every snapshot."""
+    import time
+
+    import torch
+
+    b = _lbm.Batch(problems, storage=storage, progress=progress)
+    out = torch.zeros((snapshots + 1, len(problems)) + tuple(box) + (FIELDS,), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()  # the zeros are in place before the library writes into them
+    u = problems[0].u_in
+
+    def grab(s):
+        for k, c in enumerate(b.cases):
+            c.coarse_state_into(out[s, k], factor, u)
+
+    grab(0)
+    if progress:
+        progress(f"{len(problems)} cases set up")
+    t_lbm = 0.0
+    for s in range(1, snapshots + 1):
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(horizon)
+        b.sync()
+        t_lbm += time.perf_counter() - t0
+        grab(s)
+        if progress:
+            progress(f"snapshot {s}/{snapshots}")
+    b.sync()
+    unstable = b.unstable_cases()
+    b.close()
+    return out, t_lbm, unstable
+
+
+def coarse_extent(pb, factor: int = 4):
+    """(d, h, w) of a problem's coarse lattice."""
+    return pb.nz // factor, pb.ny // factor, pb.nx // factor
+
+
+class Ensemble:
+    """`members` networks of batch size `batch` on the padded box, initialised from different
+    seeds and trained on the same pairs in different orders."""
+
+    def __init__(self, batch: int, box=BOX, members: int = 3, seed: int = 0, lr: float = 2e-3):
+        self.batch = batch
+        self.box = tuple(box)
+        self.nets = [Network(batch, *box, seed=seed + 101 * m, lr=lr) for m in range(members)]
+        self.scale = None  # per-field RMS of the change over a horizon (the networks predict change / scale)
+
+    def train(self, states, cases, steps: int, seed: int = 0):
+        """`steps` Adam steps per member on pairs (state s, change to s + 1) of the given cases
+        (states: tensor (T + 1, C, d, h, w, 4)); the change is learnt in units of its per-field
+        RMS over these pairs.  Returns each member's (first, last) mean loss over 20 steps."""
+        import torch
+
+        T = states.shape[0] - 1
+        idx = torch.as_tensor(np.asarray(cases), device=states.device)
+        sq = torch.zeros(FIELDS, dtype=torch.float64, device=states.device)
+        for s in range(T):
+            dlt = (states[s + 1, idx] - states[s, idx]).double()
+            sq += (dlt * dlt).sum(dim=(0, 1, 2, 3))
+        nvox = T * len(cases) * int(np.prod(self.box))
+        self.scale = torch.clamp((sq / nvox).sqrt(), min=1e-6).float()
+        out = []
+        for m, net in enumerate(self.nets):
+            rng = np.random.default_rng(seed + 7 * m)
+            losses = []
+            for it in range(steps):
+                s_idx = torch.from_numpy(rng.integers(0, T, size=self.batch)).cuda()
+                k_idx = torch.from_numpy(rng.choice(np.asarray(cases), size=self.batch)).cuda()
+                x = states[s_idx, k_idx].contiguous()
+                target = ((states[s_idx + 1, k_idx] - x) / self.scale).contiguous()
+                sync = it < 20 or it >= steps - 20
+                loss = net.train_step(x, target, sync_loss=sync)
+                if sync:
+                    losses.append(loss)
+            out.append((float(np.mean(losses[:20])), float(np.mean(losses[-20:]))))
+        return out
+
+    def predict(self, x):
+        """Next coarse states of x ((n, d, h, w, 4) device tensor, n <= batch) by every member:
+        a list of (n, d, h, w, 4) device tensors."""
+        import torch
+
+        n = x.shape[0]
+        xb = torch.zeros((self.batch,) + self.box + (FIELDS,), dtype=torch.float32, device=x.device)
+        xb[:n] = x
+        preds = []
+        for net in self.nets:
+            net.set_input(xb)
+            y = net.forward()
+            preds.append(x + y[:n, ..., :FIELDS] * self.scale)
+        return preds
+
+
+def predicted_interface_error(member_phis, extent) -> float:
+    """Spread of the members' interface positions (coarse cells): the largest mean
+    displacement between any two members' phi fields, on the case's coarse lattice."""
+    d, h, w = extent
+    worst = 0.0
+    for a in range(len(member_phis)):
+        for b in range(a + 1, len(member_phis)):
+            pa, pb = member_phis[a][:d, :h, :w], member_phis[b][:d, :h, :w]
+            worst = max(worst, interface_error_coarse(pa, pb), interface_error_coarse(pb, pa))
+    return worst
+
+
+def fast_forward(ens: Ensemble, states, truth, cases, extents, start: int, horizons: int, limit: float = 1.0):
+    """Advance `cases` from snapshot `start` by up to `horizons` horizons with the ensemble.
+    states: the sweep's own lattice trajectories (the fallback), truth: the plain FP32
+    lattice's, both (T + 1, C, d, h, w, 4) device tensors.  A case is advanced by the
+    ensemble mean while the predicted interface error stays within `limit` coarse cells; from
+    the first horizon where it does not, the case falls back to the lattice.  Every accepted
+    prediction is scored against the FP32 lattice (interface error in coarse cells).
+
+    Returns dict: per case the horizons taken by the surrogate, their predicted and actual
+    errors, and the actual error of the first rejected prediction (if any)."""
+    import torch
+
+    report = {}
+    for k, ext in zip(cases, extents):
+        state = states[start, k:k + 1]
+        taken, pred_err, actual_err, rejected = 0, [], [], None
+        for r in range(1, horizons + 1):
+            members = ens.predict(state)
+            phis = [p[0, ..., 0].cpu().numpy() for p in members]
+            perr = predicted_interface_error(phis, ext)
+            mean = torch.stack(members).mean(0)
+            d, h, w = ext
+            act = interface_error_coarse(mean[0, :d, :h, :w, 0].cpu().numpy(),
+                                         truth[start + r, k, :d, :h, :w, 0].cpu().numpy())
+            if perr > limit:
+                rejected = {"horizon": r, "predicted": perr, "actual": act}
+                break
+            taken += 1
+            pred_err.append(perr)
+            actual_err.append(act)
+            state = mean
+        report[k] = {"taken": taken, "predicted": pred_err, "actual": actual_err, "rejected": rejected}
+    return report
