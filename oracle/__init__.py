@@ -82,6 +82,8 @@ def lib():
         L.oracle_recolour.argtypes = [ctypes.c_double] * 5 + [_D, _D, _D, _D]
         L.oracle_collide_cell.argtypes = [ctypes.c_void_p, _D, _D, _D, _D, _D, _D, _D]
         L.oracle_gradient.argtypes = [ctypes.c_void_p, _D, _D]
+        L.oracle_A_from_sigma.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_A_from_sigma.restype = ctypes.c_double
         L.oracle_noise.argtypes = [ctypes.c_ulonglong, ctypes.c_ulonglong]
         L.oracle_noise.restype = ctypes.c_double
         _lib = L
@@ -111,7 +113,8 @@ def params_from_problem(pb, gphi_cut: float = GPHI_CUT) -> _Params:
     p = _Params()
     p.nx, p.ny, p.nz = pb.nx, pb.ny, pb.nz
     p.rho_r0, p.rho_b0, p.nu_r, p.nu_b = pb.rho_r0, pb.rho_b0, pb.nu_r, pb.nu_b
-    p.A, p.beta = pb.A, pb.beta
+    p.A = pb.A if pb.A is not None else lib().oracle_A_from_sigma(float(pb.sigma), float(pb.nu_b))
+    p.beta = pb.beta
     if pb.s is not None:
         for j in range(Q):
             p.s[j] = pb.s[j]

@@ -328,6 +328,10 @@ static double splitmix64_uniform(unsigned long long seed, unsigned long long cou
 
 double oracle_noise(unsigned long long seed, unsigned long long counter) { return splitmix64_uniform(seed, counter); }
 
+/* The surface-tension parameter of an interfacial tension sigma: Eq. (sigma), sigma = (4/9) A tau,
+ * solved for A with tau = 3 nu + 1/2 the relaxation time of the fluid of viscosity nu (R6). */
+double oracle_A_from_sigma(double sigma, double nu) { return 9.0 * sigma / (4.0 * (3.0 * nu + 0.5)); }
+
 static inline long cidx(const oracle *o, int x, int y, int z) { return ((long)z * o->p.ny + y) * o->p.nx + x; }
 static inline double *pop(double *base, const oracle *o, int k, int i) { return base + ((long)k * Q + i) * o->n; }
 

@@ -162,7 +162,10 @@ def params_from_problem(pb, storage: str = "f32") -> lbm_params:
     p = lbm_params()
     p.nx, p.ny, p.nz = pb.nx, pb.ny, pb.nz
     p.rho_r0, p.rho_b0, p.nu_r, p.nu_b = pb.rho_r0, pb.rho_b0, pb.nu_r, pb.nu_b
-    p.A, p.beta = pb.A, pb.beta
+    # a problem may give the interfacial tension instead of A: Eq. (sigma) at the continuous
+    # (blue) phase's relaxation time, converted by the library (lbm_A_from_sigma)
+    p.A = pb.A if pb.A is not None else A_from_sigma(pb.sigma, pb.nu_b)
+    p.beta = pb.beta
     if pb.s is not None:
         for j in range(Q):
             p.s[j] = pb.s[j]

@@ -50,7 +50,7 @@ class Problem:
     rho_b0: float
     nu_r: float
     nu_b: float
-    A: float
+    A: Optional[float]  # surface-tension parameter; None: derived from sigma by each implementation
     beta: float
     faces: Sequence[int] = (PERIODIC,) * 6  # -x, +x, -y, +y, -z, +z
     force_model: int = 0  # 0: none, 1: F = (rho - rho_ref) g
@@ -64,6 +64,9 @@ class Problem:
     noise_rel: float = 0.0
     seed: int = 0
     s: Optional[Sequence[float]] = None  # 27 relaxation rates or None for the defaults
+    # interfacial tension, used when A is None: each implementation converts it with Eq. (sigma)
+    # at the continuous (blue) phase's relaxation time (reading R6)
+    sigma: Optional[float] = None
     # global frame (windows of a larger domain keep the global noise counter)
     gdims: Optional[Sequence[int]] = None
     origin: Sequence[int] = (0, 0, 0)
@@ -248,21 +251,21 @@ def jet(nx: int = 256, ny: int = 256, nz: int = 1024, diameter: float = 16.0, u_
     free-slip elsewhere on that plane, convective outflow on the last plane, and sides that
     are periodic or, with ``lateral=FREESLIP``, the free-slip walls of the paper's set-up.
     rho_j = 1; sigma from We = rho_j u^2 D / sigma; g from Fr = u^2 / (g D); nu_j = eta nu_c.
-    ``A`` defaults to the surface-tension parameter that gives sigma at the relaxation time of
-    the continuous phase, sigma = (4/9) A (3 nu + 1/2)."""
+    Unless ``A`` is given, the problem carries sigma and each implementation derives the
+    surface-tension parameter from it at the continuous phase's relaxation time (Eq. (sigma),
+    reading R6)."""
     rho_r0 = 1.0
     rho_b0 = rho_r0 / gamma
     nu_j = eta * nu_c
     sigma = rho_r0 * u_in ** 2 * diameter / weber
     g = u_in ** 2 / (froude * diameter)
-    if A is None:
-        A = 9.0 * sigma / (4.0 * (3.0 * nu_c + 0.5))
 
     def make_fields(x0, y0, z0, wx, wy, wz):
         shape = (wz, wy, wx)
         return np.zeros(shape), np.full(shape, rho_b0), np.zeros((3,) + shape)
 
     pb = Problem(name="jet", nx=nx, ny=ny, nz=nz, rho_r0=rho_r0, rho_b0=rho_b0, nu_r=nu_j, nu_b=nu_c, A=A,
+                 sigma=None if A is not None else sigma,
                  beta=beta, faces=(lateral,) * 4 + (FREESLIP, OUTFLOW), force_model=1,
                  g=(0.0, 0.0, g), rho_ref=rho_b0, inflow=True, xc=(nx - 1) / 2.0, yc=(ny - 1) / 2.0,
                  diameter=diameter, u_in=u_in, noise_rel=noise_rel, seed=seed, steps=steps,
@@ -342,7 +345,7 @@ def paper_jet(case: str = "ref", fields: bool = True, lateral: int = FREESLIP) -
     breakup, Regime II), "case1" (120 x 120 x 300, varicose, Regime I) or "case2"
     (240 x 240 x 600, atomisation, Regime III), with the paper's free-slip lateral walls
     (Sec. IV A).  No inflow noise: the paper adds no perturbation, the instability grows from
-    the flow itself.  A is set from sigma at the continuous phase's relaxation time."""
+    the flow itself.  sigma is converted to A at the continuous phase's relaxation time."""
     c = PAPER_JETS[case]
     D, u = c["D"], c["u"]
     pb = jet(nx=8 * D, ny=8 * D, nz=20 * D, diameter=float(D), u_in=u, gamma=1.0 / c["rho_c"], nu_c=c["nu_c"],

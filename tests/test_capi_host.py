@@ -147,5 +147,6 @@ def test_sigma_helpers_match_table2(L):
     # the jet workload's surface-tension parameter is the same conversion at the continuous phase
     pb = W.jet(nx=32, ny=32, nz=64, diameter=8.0, u_in=0.04, weber=220.0, fields=False)
     sigma_we = pb.rho_r0 * 0.04 ** 2 * 8.0 / 220.0   # We = rho_j u^2 D / sigma, Eq. (jetWeber)
-    assert abs(lbm.sigma_from_A(pb.A, pb.nu_b) - sigma_we) <= 1e-12 * sigma_we
+    assert pb.A is None and abs(pb.sigma - sigma_we) <= 1e-15 * sigma_we
+    assert abs(lbm.sigma_from_A(lbm.params_from_problem(pb).A, pb.nu_b) - sigma_we) <= 1e-12 * sigma_we
     assert math.isnan(lbm.sigma_from_A(1e-2, 0.0)) and math.isnan(lbm.A_from_sigma(-1.0, 0.1))

@@ -11,6 +11,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 from conftest import golden_path
 from paper_1705_03141_amd import workloads as W
 
@@ -422,8 +423,9 @@ def test_paper_jet_problems_follow_the_golden_parameters():
         D = float(D)
         assert (pb.nx, pb.ny, pb.nz) == (8 * D, 8 * D, 20 * D) and pb.diameter == D
         assert pb.u_in == float(u) and pb.noise_rel == 0.0 and pb.t_unit == D / float(u)
+        A = oracle.params_from_problem(pb).A
         for got, want in ((pb.rho_b0, float(rc)), (pb.nu_r, float(nuj)), (pb.nu_b, float(nuc)), (pb.g[2], float(g)),
-                          (4 / 9 * pb.A * (3 * pb.nu_b + 0.5), float(sigma))):
+                          (pb.sigma, float(sigma)), (4 / 9 * A * (3 * pb.nu_b + 0.5), float(sigma))):
             assert abs(got - want) <= 1e-12 * want, (name, got, want)
         assert pb.rho_r0 == 1.0
 
