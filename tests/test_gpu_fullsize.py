@@ -10,6 +10,7 @@ Also here: the reduced jet (64 x 64 x 256, D = 8) over 1000 steps, per-colour ma
 1000 full-size Rayleigh-Taylor steps, and the interface-position error of FP16 and BF16
 storage against FP32 storage.
 """
+import os
 import sys
 
 import numpy as np
@@ -65,6 +66,33 @@ def test_rayleigh_taylor_fullsize_window(oracle_lib):
     log("[fullsize] Rayleigh-Taylor 128x128x512")
     e = window_parity(oracle_lib, pb, 40, 240, 32)
     assert e["rho"] < TOL and e["rho_r"] < TOL and e["rho_b"] < TOL and e["u"] < TOL, e
+
+
+def test_rayleigh_taylor_fullsize_1000_steps():
+    """The full Rayleigh-Taylor lattice (128 x 128 x 512) over the parity criterion's 1000
+    steps, in the launch configuration bench.py times, against the FP64 oracle's fields on
+    four planes (the lower wall plane and three through the perturbed interface), element by
+    element.  The oracle's planes were written by tests/golden/make_rt_fullsize_golden.py
+    (about 1.5 hours of the oracle on 8 host cores) and are normalised, as everywhere, by the
+    oracle's maxima over the whole lattice."""
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "rt128x128x512_1000steps_planes.npz"))
+    pb = W.cfg_rayleigh_taylor()
+    assert int(g["steps"]) == 1000
+    lat = lbm.Lattice(pb)
+    lat.step(1000)
+    planes = [int(z) for z in g["planes"]]
+    got = {"rho_r": np.stack([lat.field_box("rho_r", 0, 0, z, pb.nx, pb.ny, 1)[0] for z in planes]),
+           "rho_b": np.stack([lat.field_box("rho_b", 0, 0, z, pb.nx, pb.ny, 1)[0] for z in planes]),
+           "u": np.stack([np.stack([lat.field_box(k, 0, 0, z, pb.nx, pb.ny, 1)[0] for z in planes])
+                          for k in ("ux", "uy", "uz")])}
+    lat.close()
+    rho_max, u_max = float(g["max_rho"]), float(g["max_u"])
+    e = {k: float(np.abs(got[k] - g[k].astype(np.float64)).max() / rho_max) for k in ("rho_r", "rho_b")}
+    e["rho"] = float(np.abs(got["rho_r"] + got["rho_b"] - g["rho_r"].astype(np.float64)
+                            - g["rho_b"].astype(np.float64)).max() / rho_max)
+    e["u"] = float(np.abs(got["u"] - g["u"].astype(np.float64)).max() / u_max)
+    log(f"[fullsize] RT 128x128x512, 1000 steps, planes {planes}: " + " ".join(f"{k}={v:.3e}" for k, v in e.items()))
+    assert max(e.values()) < TOL, e
 
 
 def test_jet_fullsize_window(oracle_lib):
