@@ -72,7 +72,7 @@ typedef struct {
   int force;             /* 0: no body force; 1: F = (rho - rho_ref) g */
   double g[3];
   double rho_ref;
-  lbm_storage storage;
+  int storage;           /* an lbm_storage value; others are rejected with LBM_EINVAL */
 } lbm_params;
 
 /* Interfacial tension of the perturbation operator, Eq. (sigma): sigma = (4/9) A tau in
