@@ -38,7 +38,12 @@ PEAK_GBS = 8000.0
 # HBM bytes per step-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
 # scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000), per
 # workload; valid only for the kernel sources and tile shape they were taken on.
-COUNTERS = {}
+COUNTERS = {
+    "jet_256x256x1024": {"sources_sha16": "932a84b41b7b615c", "storage": "f32", "fetch_kib": 4627584.3, "fetch_scale": 2.0,
+                         "write_kib": 8388608.0, "write_scale": 1.0, "tile": [64, 4]},
+    "rayleigh_taylor_128x128x512": {"sources_sha16": "932a84b41b7b615c", "storage": "f32", "fetch_kib": 555718.2,
+                                    "fetch_scale": 2.0, "write_kib": 1048576.0, "write_scale": 1.0, "tile": [64, 4]},
+}
 KERNEL_SOURCES = ["csrc/lbm_cell.h", "csrc/lbm_device.h", "csrc/lbm_kernels.h", "csrc/lbm_kernels_impl.h",
                   "csrc/lbm_step.h", "csrc/lbm_storage_f32.hip", "build.py"]
 STD_BYTES = 432.0  # 2 colours x 27 populations x 4 B, read + write

@@ -351,6 +351,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   PlaneState bufA, bufB;
   bufA.clear();
   bufB.clear();
+  bool bad = false;  // a collided cell had a NaN, infinite or non-positive density
 
   if constexpr (!INIT) {
     stage_load(z0 - 2);
@@ -495,8 +496,9 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           gp[1] *= two;
           gp[2] *= two;
         }
-        // instability: a NaN anywhere in the pulled populations reaches rho
-        if (!(cur.rho > 0.0f && cur.rho < 3.0e38f)) *A.unstable = 1;
+        // instability: a NaN anywhere in the pulled populations reaches rho (noted here, stored
+        // once when the workgroup leaves)
+        bad |= !(cur.rho > 0.0f && cur.rho < 3.0e38f);
         CellOut o;
         collide_cell(A.cp, A.rates, cur.df, cur.shift, cur.drho, cur.rho, cur.rho_r, cur.rho_b, gp, gr, o);
 #pragma unroll
@@ -515,6 +517,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
     pass(p, bufA, bufB);
     if (p + 1 < z1) pass(p + 1, bufB, bufA);
   }
+  if (bad) *A.unstable = 1;
 }
 
 template <typename T, int TX, int TY, bool INIT, bool LAT>
