@@ -7,12 +7,13 @@
 // of a cell needs the densities of time t of its 26 neighbours, so the 2(TX+2)+2TY cells of
 // the ring around the column are pulled as well (densities only), each by one of the first
 // threads.  Per plane counter p the workgroup
-//   1. loads the scalars (e, psi, w) of source plane p+3 with a 2-cell halo and issues the 27
-//      population loads of the cells of plane p+1 (and of its ring cells) into registers,
-//   2. writes the scalars, decoded into (e, a, b, w), into an LDS ring of 4 planes (the pull
-//      reads planes p..p+2, stored before the previous barrier),
-//   3. completes the pull of plane p+1 (the population loads have been in flight since 1)
-//      and writes rho_r/rho, rho_b/rho and rho of its cells and ring into an LDS ring of 4
+//   1. issues the loads of the scalars (e, psi, w) of source plane p+3 with a 2-cell halo and
+//      the 27 population loads of the cells of plane p+1 (and of its ring cells),
+//   2. completes the pull of plane p+1, consuming the population loads in the order they
+//      were issued, and writes rho_r/rho, rho_b/rho and rho of its cells and ring into an
+//      LDS ring of 4 planes (the pull reads the staged scalars of planes p..p+2, stored in
+//      earlier passes),
+//   3. writes the scalars of plane p+3, decoded into (e, a, b, w), into an LDS ring of 4
 //      planes; barrier (the only one per plane),
 //   4. collides plane p with the gradient taken from the density ring, and stores 27
 //      deviations + 5 scalars per cell.
@@ -53,6 +54,8 @@ struct Word<float> {
   }
   static __device__ __forceinline__ float dec(W v) { return __uint_as_float(v); }
   static __device__ __forceinline__ W enc(float f) { return __float_as_uint(f); }
+  static constexpr float kPullScale = 1.0f;
+  static __device__ __forceinline__ float dec_scaled(W v) { return dec(v); }
 };
 template <>
 struct Word<_Float16> {
@@ -65,6 +68,12 @@ struct Word<_Float16> {
   }
   static __device__ __forceinline__ float dec(W v) { return Codec<_Float16>::dec(__builtin_bit_cast(_Float16, v)); }
   static __device__ __forceinline__ W enc(float f) { return __builtin_bit_cast(W, Codec<_Float16>::enc(f)); }
+  // The pull works on deviations times the storage scale: the stored half then enters an FMA
+  // as it is (converted inside the instruction).  Every scaled product and sum is the
+  // unscaled one times a power of two wherever the unscaled one is a normal number; only
+  // products below about 1e-38 (of a vanishing minority fraction) round differently.
+  static constexpr float kPullScale = Codec<_Float16>::kScale;
+  static __device__ __forceinline__ float dec_scaled(W v) { return (float)__builtin_bit_cast(_Float16, v); }
 };
 template <>
 struct Word<bf16> {
@@ -77,6 +86,8 @@ struct Word<bf16> {
   }
   static __device__ __forceinline__ float dec(W v) { return Codec<bf16>::dec(bf16{v}); }
   static __device__ __forceinline__ W enc(float f) { return Codec<bf16>::enc(f).bits; }
+  static constexpr float kPullScale = 1.0f;
+  static __device__ __forceinline__ float dec_scaled(W v) { return dec(v); }
 };
 
 __device__ __forceinline__ float load_f32(rsrc_t r, unsigned vo, int so) {
@@ -157,13 +168,16 @@ __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], 
   const float rho_old = rho_of(C, e_self, a_self, b_self);
   const float E_self = add_nc(C.E0, e_self);
   const float sgn = track_red ? 1.0f : -1.0f;  // recolouring adds to red, removes from blue
-  const float qE[4] = {0.0f, mul_nc(q_of(1), E_self), mul_nc(q_of(7), E_self), mul_nc(q_of(19), E_self)};
-  const float sq[4] = {0.0f, sgn * qc_of(1), sgn * qc_of(7), sgn * qc_of(19)};
+  // the sums run on deviations times SC (the storage scale of FP16 storage, else 1); SC is a
+  // power of two, so the scaled products and sums are exact scalings of the unscaled ones
+  constexpr float SC = Word<T>::kPullScale;
+  const float qE[4] = {0.0f, mul_nc(q_of(1) * SC, E_self), mul_nc(q_of(7) * SC, E_self), mul_nc(q_of(19) * SC, E_self)};
+  const float sq[4] = {0.0f, sgn * (qc_of(1) * SC), sgn * (qc_of(7) * SC), sgn * (qc_of(19) * SC)};
   // Every operation below is spelled out (fmaf or an *_nc operation) so that the compiler
   // cannot contract it differently in the cell and ring instances of this function: a cell's
   // densities are then bitwise the same whichever workgroup pulls it, and results do not
   // depend on the tiling.
-  float d_rho = Word<T>::dec(ld[0]);
+  float d_rho = Word<T>::dec_scaled(ld[0]);
   float d_t = mul_nc(t_self, d_rho);
   if constexpr (WANT_DF) df[0] = d_rho;
   static_for<1, Q>([&](auto ic) {
@@ -193,10 +207,10 @@ __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], 
     if constexpr ((s.ccx != 0 || s.ccy != 0) && s.ccz != 0) cw = add_nc(cw, wz);
     float d, inc;
     if constexpr (self_src) {
-      d = Word<T>::dec(ld[i]);
+      d = Word<T>::dec_scaled(ld[i]);
       inc = fmaf(sq[sh], cw, mul_nc(t_self, d));
     } else {
-      d = fmaf(q_of(i), sub_nc(src.x, e_self), Word<T>::dec(ld[i]));
+      d = fmaf(q_of(i) * SC, sub_nc(src.x, e_self), Word<T>::dec_scaled(ld[i]));
       const float t = track_red ? src.y : src.z;
       inc = fmaf(sq[sh], cw, fmaf(qE[sh], sub_nc(t, t_self), mul_nc(t, d)));
     }
@@ -204,6 +218,13 @@ __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], 
     d_t = add_nc(d_t, inc);
     if constexpr (WANT_DF) df[i] = d;
   });
+  if constexpr (SC != 1.0f) {
+    d_rho = mul_nc(d_rho, 1.0f / SC);
+    d_t = mul_nc(d_t, 1.0f / SC);
+    if constexpr (WANT_DF)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) df[i] = mul_nc(df[i], 1.0f / SC);
+  }
   rho = add_nc(rho_old, d_rho);
   const float rho_t = fmaf(t_self, rho_old, d_t), rho_o = sub_nc(rho, rho_t);
   rho_r = track_red ? rho_t : rho_o;
@@ -273,8 +294,18 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   // the collision (their slot held p-3, last read two barriers earlier).
   __shared__ float4 sS[4][NS];  // staged scalars (e, a, b, w_x) of source planes
   __shared__ float2 sW[4][NS];  // (w_y, w_z)
-  __shared__ float4 sD[4][ND];  // (rho_r/rho, rho_b/rho, rho) of time t, 1-cell ring
+  // (rho_r/rho, rho, rho_b/rho, rho) of time t, 1-cell ring: a reader takes the pair of its
+  // minority colour's fraction and rho with one 8-byte read at offset 0 or 8
+  __shared__ float4 sD[4][ND];
   auto slot4 = [](int q) { return q & 3; };
+  // Issue order of a pass's loads (measured): with FP32 populations the staged scalars go
+  // first, with 16-bit populations after the population loads.  Their LDS write waits until
+  // the pull is complete, so that the pull consumes each population load as soon as it and
+  // the older loads have arrived, rather than after all of them.  The lateral-wall instance,
+  // which spills, keeps the scalars first and their LDS write before the pull (10 % faster
+  // there).
+  constexpr bool kStoreLate = !LAT;
+  constexpr bool kStageFirst = LAT || sizeof(T) == 4;
 
   const Geo& G = A.geo;
   const bool zper = G.face_lo == FACE_PERIODIC;
@@ -376,8 +407,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
     // same SIMD are usually colliding meanwhile: the pull takes the higher issue priority so
     // that its loads go out, and the barrier is reached, sooner.
     __builtin_amdgcn_s_setprio(1);
-    // 1. scalars of plane p+3, then the populations of plane p+1
-    if constexpr (!INIT) stage_load(p + 3);
+    // 1. the loads of the scalars of plane p+3 and of the populations of plane p+1
+    if constexpr (!INIT && kStageFirst) stage_load(p + 3);
     __builtin_amdgcn_sched_barrier(0);
     typename Word<T>::W ldI[Q], ldR[Q];
     if (loads_q) {
@@ -395,12 +426,11 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
         issue_pull<T, decltype(M)::value, LAT>(slab, pb, oI, wfI, ldI);
       });
     }
+    if constexpr (!INIT && !kStageFirst) stage_load(p + 3);
     __builtin_amdgcn_sched_barrier(0);
-    // 2. staged scalars to LDS (planes p..p+2, which the pull reads, were stored in earlier
-    // passes, before the last barrier)
-    if constexpr (!INIT) stage_store(p + 3);
+    if constexpr (!INIT && !kStoreLate) stage_store(p + 3);
 
-    // 3. complete the pull of plane q: own cell (with deviations) and ring cell (densities).
+    // 2. complete the pull of plane q: own cell (with deviations) and ring cell (densities).
     // The LDS bases are made opaque per pass so that the compiler does not hoist one address
     // per neighbour out of the plane loop.
     int bI = sI - SX - 1, bR = sR - SX - 1;
@@ -429,7 +459,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           r_b = 0.0f;
         }
         const float r_inv = rcp(r_rho);
-        sD[s][dR] = make_float4(r_r * r_inv, r_b * r_inv, r_rho, 0.0f);
+        sD[s][dR] = make_float4(r_r * r_inv, r_rho, r_b * r_inv, r_rho);
       }
       if constexpr (INIT) {
         init_cell<true>(A.init, A.pc, G.n, (long long)zq * plane + col, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e, nxt.df);
@@ -449,8 +479,12 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
         nxt.rho_b = 0.0f;
       }
       const float inv = rcp(nxt.rho);
-      sD[s][dI] = make_float4(nxt.rho_r * inv, nxt.rho_b * inv, nxt.rho, 0.0f);
+      sD[s][dI] = make_float4(nxt.rho_r * inv, nxt.rho, nxt.rho_b * inv, nxt.rho);
     }
+    // 3. the staged scalars to LDS, after the pull: planes p..p+2, which the pull reads, were
+    // stored in earlier passes, and the slot written here held plane p-1, last read before the
+    // previous barrier
+    if constexpr (!INIT && kStoreLate) stage_store(p + 3);
     __builtin_amdgcn_s_setprio(0);
     __syncthreads();
 
@@ -473,6 +507,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           float vp[3][3][3], vr[3][3][3];
           int b0 = dI - DX - 1;
           asm volatile("" : "+v"(b0));
+          // (a, rho) or (b, rho) of each neighbour, by the cell's minority colour
+          const float2* D2 = reinterpret_cast<const float2*>(&sD[0][0]) + (red_minor ? 0 : 1);
           const int slots[3] = {sm, s0, sp};
           // beyond a lateral wall the stencil sees the boundary cell (reading R9)
           const int xo[3] = {(wfI & 1) ? 1 : 0, 1, (wfI & 2) ? 1 : 2};
@@ -483,9 +519,9 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
               for (int dx = 0; dx < 3; ++dx) {
-                const float4 v = sD[slots[dz]][b0 + yo[dy] + xo[dx]];
-                vp[dz][dy][dx] = red_minor ? v.x : v.y;
-                vr[dz][dy][dx] = v.z;
+                const float2 v = D2[2 * (slots[dz] * ND + b0 + yo[dy] + xo[dx])];
+                vp[dz][dy][dx] = v.x;
+                vr[dz][dy][dx] = v.y;
               }
             __builtin_amdgcn_sched_barrier(0);  // one plane of reads at a time
           }
