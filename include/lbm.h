@@ -244,6 +244,16 @@ void lbm_batch_destroy(lbm_batch *batch);
 lbm_status lbm_selftest_collide_host(const lbm_params *params, const double *fr, const double *fb,
                                      const double *grad_phi, const double *grad_rho, double *out_r, double *out_b);
 
+/* Diagnostic, not used by lbm_step: how a step with tile shape tx x ty (32x4, 32x8, 64x4,
+ * 64x8 or 32x16) distributes the tiles of a lattice with these parameters over its launches.
+ * counts (caller-owned, 3 * tiles_x * tiles_y ints, tiles_x = ceil(nx/tx), tiles_y =
+ * ceil(ny/ty), tile (i, j) at j * tiles_x + i) receives for each tile how many times the launch
+ * over all tiles (block 0), over the interior tiles (block 1) and over the frame tiles (block 2)
+ * would process it.  Without lateral walls one launch covers all tiles; with free-slip x or y
+ * faces the interior tiles (none of whose cells or ring cells lies on a wall) take the plain
+ * pull and the frame the reflecting instance.  LBM_EINVAL for invalid parameters or shapes. */
+lbm_status lbm_selftest_tile_sets_host(const lbm_params *params, int tx, int ty, int *counts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,8 @@ struct lbm_ctx {
   long long step = 0;
   bool initialised = false;
   int tx = 0, ty = 0, zchunk = 0;  // 0: chosen at the first step (choose_tiling, auto_zchunk)
+  int zchunk_in = 0, zchunk_fr = 0;  // with lateral walls and an automatic zchunk: the z chunks
+                                     // of the interior and the frame launch (0: zchunk)
   bool in_batch = false;           // advanced only by lbm_batch_step
   bool frozen = false;             // a batch case found unstable: no longer stepped
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -275,6 +277,7 @@ extern "C" lbm_status lbm_set_tiling(lbm_ctx* c, int tx, int ty, int zchunk) {
   c->tx = tx;
   c->ty = ty;
   c->zchunk = zchunk;
+  c->zchunk_in = c->zchunk_fr = 0;
   return LBM_OK;
 }
 
@@ -323,9 +326,9 @@ extern "C" lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_r, const dou
 
 // Planes per workgroup when none is set: the number of z chunks that minimises
 // (rounds of resident workgroups) x (planes per chunk + the 2 planes each chunk pulls first).
-static int auto_zchunk(const lbm_ctx* c) {
+static int zchunk_for(const lbm_ctx* c, long long tiles) {
   const Geo& G = c->geo;
-  const long long tiles = (long long)((G.nx + c->tx - 1) / c->tx) * ((G.ny + c->ty - 1) / c->ty);
+  if (tiles < 1) return G.nz;
   int dev = 0;
   (void)hipGetDevice(&dev);
   long long resident = step_resident_blocks((int)c->p.storage, c->tx, c->ty, dev);
@@ -345,6 +348,13 @@ static int auto_zchunk(const lbm_ctx* c) {
   return best;
 }
 
+static int auto_zchunk(const lbm_ctx* c) {
+  const Geo& G = c->geo;
+  return zchunk_for(c, (long long)((G.nx + c->tx - 1) / c->tx) * ((G.ny + c->ty - 1) / c->ty));
+}
+
+static void fill_step_args(const lbm_ctx* c, int cur, int out_cur, StepArgs& s);
+
 static void choose_tiling(lbm_ctx* c) {
   if (c->tx == 0) {
     // measured on MI355X: 64 x 4 tiles on rows of 64 cells or more, 32 x 8 otherwise
@@ -353,7 +363,25 @@ static void choose_tiling(lbm_ctx* c) {
     c->tx = wide ? 64 : 32;
     c->ty = wide ? 4 : 8;
   }
-  if (c->zchunk < 1) c->zchunk = auto_zchunk(c);
+  if (c->zchunk < 1) {
+    c->zchunk = auto_zchunk(c);
+    c->zchunk_in = c->zchunk_fr = 0;
+    if (c->geo.wall_x || c->geo.wall_y) {
+      // the interior and the frame run as two launches, one after the other: each is chunked
+      // in z to fill the device by itself
+      StepArgs s{};
+      fill_step_args(c, 0, 0, s);
+      s.tile_set = kInteriorTiles;
+      c->zchunk_in = zchunk_for(c, tiles_in_set(s));
+      s.tile_set = kFrameTiles;
+      c->zchunk_fr = zchunk_for(c, tiles_in_set(s));
+    }
+  }
+}
+
+static void set_zchunk(const Geo& G, int zchunk, StepArgs& s) {
+  s.zchunk = zchunk;
+  s.nchunks = (G.nz + zchunk - 1) / zchunk;
 }
 
 // Arguments of the step kernel for the state of parity cur (outlet record out_cur).
@@ -371,6 +399,22 @@ static void fill_step_args(const lbm_ctx* c, int cur, int out_cur, StepArgs& s) 
   s.tiles_x = (G.nx + c->tx - 1) / c->tx;
   s.tiles_y = (G.ny + c->ty - 1) / c->ty;
   s.nchunks = (G.nz + c->zchunk - 1) / c->zchunk;
+  // interior rectangle: tiles whose own and ring cells are all off the lateral walls, i.e.
+  // tile index >= 1 and (index + 1) * tile width <= n - 2 along each axis that has walls
+  s.tile_set = kAllTiles;
+  s.tx_lo = 0;
+  s.tx_hi = s.tiles_x;
+  s.ty_lo = 0;
+  s.ty_hi = s.tiles_y;
+  if (G.wall_x) {
+    s.tx_lo = 1;
+    s.tx_hi = (G.nx - 2) / c->tx;
+  }
+  if (G.wall_y) {
+    s.ty_lo = 1;
+    s.ty_hi = (G.ny - 2) / c->ty;
+  }
+  if (s.tx_hi <= s.tx_lo || s.ty_hi <= s.ty_lo) s.tx_lo = s.tx_hi = s.ty_lo = s.ty_hi = 0;
   s.unstable = c->unstable;
   s.skip_unstable = c->in_batch ? 1 : 0;
   s.geo = G;
@@ -399,7 +443,20 @@ static lbm_status enqueue_one(lbm_ctx* c) {
   StepArgs s{};
   choose_tiling(c);
   fill_step_args(c, c->cur, c->out_cur, s);
-  hipError_t e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
+  hipError_t e = hipSuccess;
+  if (G.wall_x || G.wall_y) {
+    // the interior tiles with the plain pull, the frame with the reflecting instance
+    if (s.tx_hi > s.tx_lo) {
+      s.tile_set = kInteriorTiles;
+      set_zchunk(G, c->zchunk_in > 0 ? c->zchunk_in : c->zchunk, s);
+      e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
+    }
+    s.tile_set = kFrameTiles;
+    set_zchunk(G, c->zchunk_fr > 0 ? c->zchunk_fr : c->zchunk, s);
+    if (e == hipSuccess) e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
+  } else {
+    e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "step kernel");
   if (G.inflow) {
     e = launch_inflow((int)c->p.storage, s, c->stream);
@@ -661,6 +718,7 @@ extern "C" lbm_status lbm_load_state(lbm_ctx* c, const void* src, size_t bytes) 
 struct BatchGroup {
   int storage = 0, tx = 0, ty = 0;
   bool lat = false;                     // lateral free-slip walls (a separate kernel instance)
+  int tile_set = kAllTiles;             // the tiles of each case the group's launch covers
   std::vector<int> cases;               // indices into lbm_batch::c
   StepArgs* d_args[2] = {nullptr, nullptr};  // device tables for parity 0 and 1
   int* d_first = nullptr;               // device block offsets (ncases + 1)
@@ -781,13 +839,11 @@ static void batch_tiling(lbm_batch* b) {
 
 static lbm_status build_groups(lbm_batch* b) {
   free_groups(b);
-  for (int k = 0; k < (int)b->c.size(); ++k) {
+  auto add = [&](int k, bool lat, int set) {
     const lbm_ctx* c = b->c[k];
-    if (c->frozen) continue;
     BatchGroup* g = nullptr;
-    const bool lat = c->geo.wall_x || c->geo.wall_y;
     for (auto& x : b->groups)
-      if (x.storage == (int)c->p.storage && x.tx == c->tx && x.ty == c->ty && x.lat == lat) g = &x;
+      if (x.storage == (int)c->p.storage && x.tx == c->tx && x.ty == c->ty && x.lat == lat && x.tile_set == set) g = &x;
     if (!g) {
       b->groups.emplace_back();
       g = &b->groups.back();
@@ -795,8 +851,22 @@ static lbm_status build_groups(lbm_batch* b) {
       g->tx = c->tx;
       g->ty = c->ty;
       g->lat = lat;
+      g->tile_set = set;
     }
     g->cases.push_back(k);
+  };
+  for (int k = 0; k < (int)b->c.size(); ++k) {
+    const lbm_ctx* c = b->c[k];
+    if (c->frozen) continue;
+    if (c->geo.wall_x || c->geo.wall_y) {
+      // with lateral walls: the interior tiles in a plain group, the frame in a reflecting one
+      StepArgs s{};
+      fill_step_args(c, 0, 0, s);
+      if (s.tx_hi > s.tx_lo) add(k, false, kInteriorTiles);
+      add(k, true, kFrameTiles);
+    } else {
+      add(k, false, kAllTiles);
+    }
   }
   for (auto& g : b->groups) {
     const int n = (int)g.cases.size();
@@ -807,10 +877,11 @@ static lbm_status build_groups(lbm_batch* b) {
       for (int par = 0; par < 2; ++par) {
         StepArgs s{};
         fill_step_args(c, par, par, s);
+        s.tile_set = g.tile_set;
         h[par].push_back(s);
       }
       const StepArgs& s = h[0].back();
-      const long long blocks = (long long)s.tiles_x * s.tiles_y * s.nchunks;
+      const long long blocks = (long long)tiles_in_set(s) * s.nchunks;
       first[j + 1] = first[j] + (int)((blocks + 7) / 8 * 8);
     }
     g.nblocks = first[n];
@@ -1071,7 +1142,39 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps) {
   return LBM_OK;
 }
 
-// ---------------------------------------------------------------- host self-check
+// ---------------------------------------------------------------- host self-checks
+extern "C" lbm_status lbm_selftest_tile_sets_host(const lbm_params* params, int tx, int ty, int* counts) {
+  if (!params || !counts) return LBM_EINVAL;
+  if (!((tx == 32 && (ty == 4 || ty == 8 || ty == 16)) || (tx == 64 && (ty == 4 || ty == 8)))) return LBM_EINVAL;
+  lbm_ctx tmp;
+  tmp.p = *params;
+  std::string msg;
+  lbm_status st = check_params(params, &tmp, msg);
+  if (st != LBM_OK) return fail(nullptr, st, msg);
+  tmp.tx = tx;
+  tmp.ty = ty;
+  tmp.zchunk = tmp.geo.nz;
+  StepArgs s{};
+  fill_step_args(&tmp, 0, 0, s);
+  const int nt = s.tiles_x * s.tiles_y;
+  for (int k = 0; k < 3 * nt; ++k) counts[k] = 0;
+  const bool walls = tmp.geo.wall_x || tmp.geo.wall_y;
+  const int sets[3] = {kAllTiles, kInteriorTiles, kFrameTiles};
+  for (int b = 0; b < 3; ++b) {
+    // the launches enqueue_one makes: one over all tiles without walls, else interior + frame
+    if ((sets[b] == kAllTiles) == walls) continue;
+    s.tile_set = sets[b];
+    const int n = tiles_in_set(s);
+    for (int t = 0; t < n; ++t) {
+      int i = -1, j = -1;
+      tile_of(s, t, i, j);
+      if (i < 0 || i >= s.tiles_x || j < 0 || j >= s.tiles_y) return fail(nullptr, LBM_EDEVICE, "tile out of range");
+      counts[b * nt + j * s.tiles_x + i]++;
+    }
+  }
+  return LBM_OK;
+}
+
 extern "C" lbm_status lbm_selftest_collide_host(const lbm_params* params, const double* fr, const double* fb,
                                                 const double* grad_phi, const double* grad_rho, double* out_r,
                                                 double* out_b) {

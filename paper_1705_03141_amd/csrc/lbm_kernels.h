@@ -31,6 +31,8 @@ struct StepArgs {
   long long step;
   int init_mode;
   int zchunk, tiles_x, tiles_y, nchunks;
+  int tile_set;          // kAllTiles, kInteriorTiles or kFrameTiles
+  int tx_lo, tx_hi, ty_lo, ty_hi;  // the interior rectangle of tiles [tx_lo, tx_hi) x [ty_lo, ty_hi)
   int* unstable;         // set to 1 by a cell whose density is NaN, infinite or <= 0
   int skip_unstable;     // 1: workgroups of a flagged lattice return at once (batches)
   Geo geo;
@@ -38,6 +40,46 @@ struct StepArgs {
   CollideParams cp;
   GroupRates rates;
 };
+
+// The tiles one launch of the step kernel covers.  With lateral walls the tiles whose cells
+// and ring cells are all off the walls (the interior rectangle) take the plain pull, and only
+// the frame of tiles around it the instance that reflects at the walls.
+enum TileSet { kAllTiles = 0, kInteriorTiles = 1, kFrameTiles = 2 };
+
+__host__ __device__ inline int tiles_in_set(const StepArgs& a) {
+  const int all = a.tiles_x * a.tiles_y, inner = (a.tx_hi - a.tx_lo) * (a.ty_hi - a.ty_lo);
+  return a.tile_set == kAllTiles ? all : (a.tile_set == kInteriorTiles ? inner : all - inner);
+}
+
+// Tile (txi, tyi) of the t-th tile of the launch's set.  The frame is numbered by bands: the
+// rows below the rectangle, the rows above it, then the side pieces of its rows.
+__host__ __device__ inline void tile_of(const StepArgs& a, int t, int& txi, int& tyi) {
+  if (a.tile_set == kInteriorTiles) {
+    const int w = a.tx_hi - a.tx_lo;
+    tyi = a.ty_lo + t / w;
+    txi = a.tx_lo + t % w;
+    return;
+  }
+  if (a.tile_set == kFrameTiles) {
+    const int below = a.ty_lo * a.tiles_x, above = (a.tiles_y - a.ty_hi) * a.tiles_x;
+    if (t >= below && t < below + above) {
+      t -= below;
+      tyi = a.ty_hi + t / a.tiles_x;
+      txi = t % a.tiles_x;
+      return;
+    }
+    if (t >= below + above) {
+      t -= below + above;
+      const int side = a.tx_lo + (a.tiles_x - a.tx_hi);
+      tyi = a.ty_lo + t / side;
+      const int k = t % side;
+      txi = k < a.tx_lo ? k : a.tx_hi + (k - a.tx_lo);
+      return;
+    }
+  }
+  tyi = t / a.tiles_x;
+  txi = t - tyi * a.tiles_x;
+}
 
 // Arguments of the outlet and read-back kernels.
 struct AuxArgs {

@@ -320,13 +320,14 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   // block L of nb -> (z chunk, tile); XCD x receives blocks x, x + 8, ...: give it a
   // contiguous range (nb and the first block of the range are multiples of 8 when remapped)
   if ((nb & 7) == 0) L = (L & 7) * (nb >> 3) + (L >> 3);
-  const int ntiles = A.tiles_x * A.tiles_y;
+  const int ntiles = tiles_in_set(A);
   const int chunk = L / ntiles, tile = L - chunk * ntiles;
   if (chunk >= A.nchunks) return;  // padding block of a batch (the whole block leaves)
   // a lattice of a batch that went unstable is not stepped further (the flag is read once per
   // workgroup, before any barrier; the whole workgroup leaves)
   if (A.skip_unstable && __hip_atomic_load(A.unstable, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  const int tyi = tile / A.tiles_x, txi = tile - tyi * A.tiles_x;
+  int txi, tyi;
+  tile_of(A, tile, txi, tyi);
   const int x0 = txi * TX, y0 = tyi * TY;
   const int z0 = chunk * A.zchunk, z1 = min(z0 + A.zchunk, G.nz);
 
@@ -627,7 +628,8 @@ __global__ void __launch_bounds__(256)
 // ================================================================== launchers
 template <typename T, int TX, int TY, bool LAT>
 hipError_t launch_step_lat(const StepArgs& a, hipStream_t s) {
-  const long long blocks = (long long)a.tiles_x * a.tiles_y * a.nchunks;
+  const long long blocks = (long long)tiles_in_set(a) * a.nchunks;
+  if (blocks == 0) return hipSuccess;
   if (a.init_mode)
     hipLaunchKernelGGL((step_kernel<T, TX, TY, true, LAT>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, a);
   else
@@ -636,10 +638,11 @@ hipError_t launch_step_lat(const StepArgs& a, hipStream_t s) {
 }
 
 // The step kernel with lateral free-slip walls is a separate instance: lattices with periodic
-// sides keep the plain pull.
+// sides, and the interior tiles of a lattice with walls, keep the plain pull.
 template <typename T, int TX, int TY>
 hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
-  return (a.geo.wall_x || a.geo.wall_y) ? launch_step_lat<T, TX, TY, true>(a, s) : launch_step_lat<T, TX, TY, false>(a, s);
+  return ((a.geo.wall_x || a.geo.wall_y) && a.tile_set != kInteriorTiles) ? launch_step_lat<T, TX, TY, true>(a, s)
+                                                                          : launch_step_lat<T, TX, TY, false>(a, s);
 }
 
 template <typename T, int TX, int TY, bool LAT>

@@ -103,6 +103,7 @@ def library():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_selftest_collide_host.argtypes = [P, _D, _D, _D, _D, _D, _D]
+        L.lbm_selftest_tile_sets_host.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         for name in ("lbm_sigma_from_A", "lbm_A_from_sigma"):
             getattr(L, name).argtypes = [ctypes.c_double, ctypes.c_double]
             getattr(L, name).restype = ctypes.c_double
@@ -125,7 +126,8 @@ def library():
             getattr(L, name).restype = getattr(L, name).restype  # resolves every declared symbol
         for name in ("lbm_create", "lbm_init_fields", "lbm_set_inflow", "lbm_set_tiling", "lbm_autotune", "lbm_get_tiling", "lbm_step", "lbm_sync",
                      "lbm_read_field", "lbm_read_field_box", "lbm_read_populations", "lbm_save_state",
-                     "lbm_load_state", "lbm_diagnostics", "lbm_selftest_collide_host", "lbm_batch_create",
+                     "lbm_load_state", "lbm_diagnostics", "lbm_selftest_collide_host", "lbm_selftest_tile_sets_host",
+                     "lbm_batch_create",
                      "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_sync", "lbm_batch_size"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -422,3 +424,15 @@ def selftest_collide_host(problem, fr, fb, grad_phi, grad_rho):
                                             _ptr(_arr(grad_phi, 3)), _ptr(_arr(grad_rho, 3)), _ptr(outr), _ptr(outb))
     _check(None, st)
     return outr, outb
+
+
+def selftest_tile_sets_host(problem, tx: int, ty: int) -> np.ndarray:
+    """How the step's launches cover the tiles of tx x ty (diagnostic; no GPU): counts of shape
+    (3, tiles_y, tiles_x) for the launch over all tiles, the interior tiles and the frame."""
+    p = params_from_problem(problem)
+    ntx, nty = -(-problem.nx // tx), -(-problem.ny // ty)
+    counts = np.zeros(3 * ntx * nty, dtype=np.int32)
+    st = library().lbm_selftest_tile_sets_host(ctypes.byref(p), int(tx), int(ty),
+                                              counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    _check(None, st)
+    return counts.reshape(3, nty, ntx)

@@ -150,3 +150,32 @@ def test_sigma_helpers_match_table2(L):
     assert pb.A is None and abs(pb.sigma - sigma_we) <= 1e-15 * sigma_we
     assert abs(lbm.sigma_from_A(lbm.params_from_problem(pb).A, pb.nu_b) - sigma_we) <= 1e-12 * sigma_we
     assert math.isnan(lbm.sigma_from_A(1e-2, 0.0)) and math.isnan(lbm.A_from_sigma(-1.0, 0.1))
+
+
+@pytest.mark.parametrize("dims,faces", [((100, 44, 24), "xy"), ((256, 256, 16), "xy"), ((240, 40, 8), "x"),
+                                        ((96, 64, 8), "y"), ((70, 36, 20), ""), ((37, 29, 23), "xy")])
+def test_tile_sets_cover_every_tile_once(L, dims, faces):
+    """With lateral walls the step launches the plain pull over the interior tiles and the
+    reflecting instance over the frame: every tile is processed exactly once, and a tile is
+    interior exactly when none of its cells or ring cells lies on a wall (checked here from
+    the geometry, cell by cell)."""
+    pb = W.static_droplet(dims=dims, radius=3.0, rho_r0=1.5, rho_b0=1.0, nu=0.05, A=0.01)
+    pb.faces = (W.FREESLIP if "x" in faces else W.PERIODIC,) * 2 + (W.FREESLIP if "y" in faces else W.PERIODIC,) * 2 \
+        + (W.FREESLIP, W.FREESLIP)
+    nx, ny = dims[0], dims[1]
+    for tx, ty in ((32, 4), (32, 8), (64, 4), (64, 8), (32, 16)):
+        c = lbm.selftest_tile_sets_host(pb, tx, ty)
+        assert np.all(c.sum(axis=0) == 1), (tx, ty)
+        if not faces:
+            assert np.all(c[0] == 1)
+            continue
+        assert np.all(c[0] == 0)
+        for j in range(c.shape[1]):
+            for i in range(c.shape[2]):
+                xs = range(i * tx - 1, i * tx + tx + 1)  # own cells and the ring
+                ys = range(j * ty - 1, j * ty + ty + 1)
+                on_wall = ("x" in faces and any(x % nx in (0, nx - 1) for x in xs)) or \
+                          ("y" in faces and any(y % ny in (0, ny - 1) for y in ys))
+                assert c[1, j, i] == (0 if on_wall else 1), (tx, ty, i, j)
+    with pytest.raises(lbm.LbmError):
+        lbm.selftest_tile_sets_host(pb, 16, 16)

@@ -176,6 +176,40 @@ def test_tilings_free_slip_box(O, tiling):
     assert err < 2e-6, err
 
 
+_WALL_JET_REF = {}
+
+
+def _wall_jet():
+    return W.jet(nx=100, ny=44, nz=64, diameter=10.0, eta=4.2, seed=7, lateral=W.FREESLIP)
+
+
+@pytest.mark.parametrize("tiling", [(32, 8, 7), (32, 4, 24), (32, 16, 6)])
+def test_walls_interior_tiles_take_plain_pull(O, tiling):
+    """A 100 x 44 x 64 jet (eta = 4.2) between free-slip lateral walls: with 32-wide tiles the
+    interior tiles run the plain pull and the frame the reflecting instance, with 64 x 4 tiles
+    every tile is a frame tile.  The two agree bit for bit over 100 steps, and with the oracle
+    to the parity bar."""
+    pb = _wall_jet()
+    counts = lbm.selftest_tile_sets_host(pb, tiling[0], tiling[1])
+    assert counts[1].sum() > 0, "no interior tiles: the case would not test the split"
+    assert lbm.selftest_tile_sets_host(pb, 64, 4)[1].sum() == 0
+    log(f"[walls, interior tiles] {tiling} 100x44x64 jet")
+    lat = lbm.Lattice(pb, tiling=tiling)
+    ref_lat = lbm.Lattice(pb, tiling=(64, 4, 24))
+    lat.step(100)
+    ref_lat.step(100)
+    assert bool(np.array_equal(lat.populations(), ref_lat.populations())), "split and unsplit launches disagree"
+    if "fields" not in _WALL_JET_REF:
+        o = O.Oracle(pb)
+        o.step(100)
+        _WALL_JET_REF["fields"] = o.fields()
+    e = errors(lat.fields(), _WALL_JET_REF["fields"])
+    log("  vs oracle: " + " ".join(f"{k}={v:.3e}" for k, v in e.items()))
+    lat.close()
+    ref_lat.close()
+    assert e["rho"] < TOL and e["rho_r"] < TOL and e["rho_b"] < TOL and e["u"] < TOL, e
+
+
 def test_autotune_keeps_state_and_results():
     """lbm_autotune times the tile shapes on a scratch lattice: the context's state is
     untouched, the chosen shape is a supported one, and the steps after it agree bit for bit
