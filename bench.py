@@ -39,9 +39,9 @@ PEAK_GBS = 8000.0
 # scaled by what the counters read for a plain 1 GiB copy (fetch x2.000, write x1.000), per
 # workload; valid only for the kernel sources and tile shape they were taken on.
 COUNTERS = {
-    "jet_256x256x1024": {"sources_sha16": "932a84b41b7b615c", "storage": "f32", "fetch_kib": 4627584.3, "fetch_scale": 2.0,
+    "jet_256x256x1024": {"sources_sha16": "d0826ec4cf8a4e1d", "storage": "f32", "fetch_kib": 4803797.8, "fetch_scale": 2.0,
                          "write_kib": 8388608.0, "write_scale": 1.0, "tile": [64, 4]},
-    "rayleigh_taylor_128x128x512": {"sources_sha16": "932a84b41b7b615c", "storage": "f32", "fetch_kib": 555718.2,
+    "rayleigh_taylor_128x128x512": {"sources_sha16": "d0826ec4cf8a4e1d", "storage": "f32", "fetch_kib": 556974.0,
                                     "fetch_scale": 2.0, "write_kib": 1048576.0, "write_scale": 1.0, "tile": [64, 4]},
 }
 KERNEL_SOURCES = ["csrc/lbm_cell.h", "csrc/lbm_device.h", "csrc/lbm_kernels.h", "csrc/lbm_kernels_impl.h",
@@ -436,7 +436,10 @@ def main():
         print("bench.py: the run went unstable", file=sys.stderr)
         sys.exit(1)
     mlups = n * args.steps / wall / 1e6
-    achieved = STD_BYTES * n / (kernel_ms * 1e-3) / 1e9
+    # the standard traffic of the method at the storage width: 2 x 27 populations of 4 B
+    # (FP32) or 2 B (FP16/BF16), read and written once per update
+    std_bytes = STD_BYTES if args.storage == "f32" else STD_BYTES / 2.0
+    achieved = std_bytes * n / (kernel_ms * 1e-3) / 1e9
     extra = {"kernel_ms": kernel_ms, "state_bytes_per_update": state_bytes(args.storage),
              "state_traffic_frac": state_bytes(args.storage) * n / (kernel_ms * 1e-3) / 1e9 / PEAK_GBS}
     for st in ("f16", "bf16"):
@@ -465,8 +468,9 @@ def main():
                    "tile": list(diag["tiling"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_GBS, "traffic": traffic,
-                     "basis": "432 B per cell update (2 x 27 FP32 populations read and written) x cells / "
-                              "mean step-kernel time"},
+                     "basis": f"{std_bytes:.0f} B per cell update (2 x 27 "
+                              f"{'FP32' if args.storage == 'f32' else '16-bit'} populations read and written) "
+                              "x cells / mean step-kernel time"},
         "extra": extra,
     }
     if not args.no_cpu_baseline:
