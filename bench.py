@@ -154,7 +154,9 @@ def sweep(steps: int, warmup: int, storage: str = "f16"):
     ncells = sum(c.ncells for c in cases)
     log(f"sweep: {len(cases)} cases, {ncells / 1e6:.0f} M cells, storage {storage}")
     b = lbm.Batch(cases, storage=storage, progress=lambda m: log(f"sweep: {m}"))
-    log("sweep: initialised; autotuning")
+    free, total = torch.cuda.mem_get_info()
+    used_gb = (total - free) / 1e9  # device memory in use once every case holds its state
+    log(f"sweep: initialised, {used_gb:.1f} GB of {total / 1e9:.0f} GB in use; autotuning")
     b.autotune(trial_steps=5)
     b.step(warmup)
     b.sync()
@@ -181,7 +183,8 @@ def sweep(steps: int, warmup: int, storage: str = "f16"):
     achieved = std_bytes * ncells / (b.last_step_ms() * 1e-3) / 1e9
     print(json.dumps({"metric": "MLUPS, batched regime-map sweep (64 jet cases)", "value": mlups, "unit": "MLUPS",
                       "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3 / steps, "dtype": f"f32 compute, {storage} storage",
-                      "config": {"workload": "regime_sweep_64_jets", "cases": len(cases), "cells": ncells},
+                      "config": {"workload": "regime_sweep_64_jets", "cases": len(cases), "cells": ncells,
+                                 "device_memory_gb": used_gb},
                       "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                                    "frac": achieved / PEAK_GBS, "bytes_per_cell": std_bytes},
                       "unstable_cases": unstable,
@@ -381,6 +384,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--sweep-storage", default="f16", choices=["f32", "f16", "bf16"],
+                    help="population storage of --sweep (the sweep is specified in FP16)")
     ap.add_argument("--workload", default="jet", choices=["rt", "jet"],
                     help="jet: the liquid jet 256 x 256 x 1024 (the default); rt: Rayleigh-Taylor 128 x 128 x 512")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
@@ -413,7 +418,7 @@ def main():
         interface_error(args.interface_error, args.steps)
         return
     if args.sweep:
-        sweep(args.steps, args.warmup)
+        sweep(args.steps, args.warmup, args.sweep_storage)
         return
     if args.surrogate:
         surrogate_bench(args.steps, args.warmup)
