@@ -284,6 +284,7 @@ struct GroupRates {
 // with meq = M (f_eq - rho varphi(alpha_bar)) from Eqs. (EES), (Phi), mF = M F' from
 // Eq. (ketFd) and G mP = M Omega2 from Eq. (perturb), each a closed form of
 // (rho, u, grad rho, F, n) obtained by applying the rows of Eq. (momentSet) to them.
+template <int OUT_SHIFT = 0>
 __host__ __device__ inline void collide_cell(const CollideParams& P, const GroupRates& S, const float (&df)[Q],
                                              float shift, float drho, float rho, float rho_r, float rho_b,
                                              const float (&gp)[3], const float (&gr)[3], CellOut& out) {
@@ -350,12 +351,14 @@ __host__ __device__ inline void collide_cell(const CollideParams& P, const Group
   const float pe7 = k9 * nx * ny, pe8 = k9 * ny * nz, pe9 = k9 * nx * nz;
 
   float y[Q];
+  // the outputs come out times 2^OUT_SHIFT (the storage scale of FP16), folded into 1/D_j
+  constexpr float os = (float)(1 << OUT_SHIFT);
   // conserved: mass, momentum (+F)
-  y[0] = m[0] * inv_norm(0);
-  y[1] = (m[1] + Fx) * inv_norm(1);
-  y[2] = (m[2] + Fy) * inv_norm(2);
-  y[3] = (m[3] + Fz) * inv_norm(3);
-#define LBM_RELAX(j, s, eq, fo, pe) y[j] = (m[j] - (s) * (m[j] - (eq)) + (1.0f - 0.5f * (s)) * (fo) + (pe)) * inv_norm(j)
+  y[0] = m[0] * (inv_norm(0) * os);
+  y[1] = (m[1] + Fx) * (inv_norm(1) * os);
+  y[2] = (m[2] + Fy) * (inv_norm(2) * os);
+  y[3] = (m[3] + Fz) * (inv_norm(3) * os);
+#define LBM_RELAX(j, s, eq, fo, pe) y[j] = (m[j] - (s) * (m[j] - (eq)) + (1.0f - 0.5f * (s)) * (fo) + (pe)) * (inv_norm(j) * os)
   LBM_RELAX(4, S.s5, eq4, 2.0f * uF, -(4.0f / 9.0f) * G);
   LBM_RELAX(5, snu, eq5, fo5, pe5);
   LBM_RELAX(6, snu, eq6, fo6, pe6);
@@ -400,7 +403,8 @@ __host__ __device__ inline void collide_cell(const CollideParams& P, const Group
       if (CY[i] != 0) jy += (float)CY[i] * d;
       if (CZ[i] != 0) jz += (float)CZ[i] * d;
     }
-    const float hx = 0.5f * ((m[1] + Fx) - jx), hy = 0.5f * ((m[2] + Fy) - jy), hz = 0.5f * ((m[3] + Fz) - jz);
+    const float hx = 0.5f * ((m[1] + Fx) * os - jx), hy = 0.5f * ((m[2] + Fy) * os - jy),
+                hz = 0.5f * ((m[3] + Fz) * os - jz);
     out.g[1] += hx;
     out.g[2] -= hx;
     out.g[3] += hy;
@@ -409,7 +413,7 @@ __host__ __device__ inline void collide_cell(const CollideParams& P, const Group
     out.g[6] -= hz;
 #pragma unroll
     for (int i = 1; i < Q; ++i) mass += out.g[i];
-    out.g[0] = m[0] - mass;
+    out.g[0] = m[0] * os - mass;
   }
 
   // Recolouring (Latva-Kokko & Rothman), carried to the readers as rho_r/rho and
