@@ -302,15 +302,16 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   // the collision (their slot held p-3, last read two barriers earlier).
   __shared__ float4 sS[4][NS];  // staged scalars (e, a, b, w_x) of source planes
   __shared__ float2 sW[4][NS];  // (w_y, w_z)
-  // Density ring of time t with a 1-cell ring: per cell the pairs (rho_r/rho, rho) and
-  // (rho_b/rho, rho), so that a reader takes its minority colour's fraction and rho with one
-  // 8-byte read.  The two pairs lie in separate arrays, where a wave's reads of neighbouring
-  // cells fall on distinct banks; with FP16 storage they are interleaved per cell, because
-  // the separate form makes that instance spill (measured: +1.3 % FP32, +7.6 % with lateral
-  // walls, -6 % FP16 for the separate form).
+  // Density ring of time t with a 1-cell ring, 4 slots: per cell the pairs (rho_r/rho, rho)
+  // (sel 0) and (rho_b/rho, rho) (sel 1), so that a reader takes its minority colour's fraction
+  // and rho with one 8-byte read.  The two pairs lie in separate arrays of 4 slots each, where
+  // a wave's reads of neighbouring cells fall on distinct banks; with FP16 storage they are
+  // interleaved per cell, because the separate form makes that instance spill (measured on
+  // the jet: +1.3 % FP32, +7.6 % with lateral walls, -6 % FP16 for the separate form).
   constexpr bool kSplitRing = !std::is_same<T, _Float16>::value;
-  __shared__ float2 sD[4][2 * ND];
-  auto dslot = [](int sel, int d) { return kSplitRing ? sel * ND + d : 2 * d + sel; };
+  __shared__ float2 sDf[8 * ND];
+  // index of pair sel of cell d in slot s
+  auto dat = [](int s, int sel, int d) { return kSplitRing ? (sel * 4 + s) * ND + d : s * 2 * ND + 2 * d + sel; };
   auto slot4 = [](int q) { return q & 3; };
   // Issue order of a pass's loads (measured): with FP32 populations the staged scalars go
   // first, with 16-bit populations after the population loads.  Their LDS write waits until
@@ -474,8 +475,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           r_b = 0.0f;
         }
         const float r_inv = rcp(r_rho);
-        sD[s][dslot(0, dR)] = make_float2(r_r * r_inv, r_rho);
-        sD[s][dslot(1, dR)] = make_float2(r_b * r_inv, r_rho);
+        sDf[dat(s, 0, dR)] = make_float2(r_r * r_inv, r_rho);
+        sDf[dat(s, 1, dR)] = make_float2(r_b * r_inv, r_rho);
       }
       if constexpr (INIT) {
         init_cell<true>(A.init, A.pc, G.n, (long long)zq * plane + col, nxt.rho, nxt.rho_r, nxt.rho_b, nxt.e, nxt.df);
@@ -495,8 +496,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
         nxt.rho_b = 0.0f;
       }
       const float inv = rcp(nxt.rho);
-      sD[s][dslot(0, dI)] = make_float2(nxt.rho_r * inv, nxt.rho);
-      sD[s][dslot(1, dI)] = make_float2(nxt.rho_b * inv, nxt.rho);
+      sDf[dat(s, 0, dI)] = make_float2(nxt.rho_r * inv, nxt.rho);
+      sDf[dat(s, 1, dI)] = make_float2(nxt.rho_b * inv, nxt.rho);
     }
     // 3. the staged scalars to LDS, after the pull: planes p..p+2, which the pull reads, were
     // stored in earlier passes, and the slot written here held plane p-1, last read before the
@@ -525,8 +526,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
           int b0 = dI - DX - 1;
           asm volatile("" : "+v"(b0));
           // (a, rho) or (b, rho) of each neighbour, by the cell's minority colour
-          const float2* D2 = &sD[0][0] + dslot(red_minor ? 0 : 1, 0);
-          constexpr int kCellStride = kSplitRing ? 1 : 2;
+          const float2* D2 = sDf + dat(0, red_minor ? 0 : 1, 0);
+          constexpr int kCellStride = kSplitRing ? 1 : 2, kSlotStride = kSplitRing ? ND : 2 * ND;
           const int slots[3] = {sm, s0, sp};
           // beyond a lateral wall the stencil sees the boundary cell (reading R9)
           const int xo[3] = {(wfI & 1) ? 1 : 0, 1, (wfI & 2) ? 1 : 2};
@@ -537,7 +538,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
               for (int dx = 0; dx < 3; ++dx) {
-                const float2 v = D2[slots[dz] * 2 * ND + kCellStride * (b0 + yo[dy] + xo[dx])];
+                const float2 v = D2[slots[dz] * kSlotStride + kCellStride * (b0 + yo[dy] + xo[dx])];
                 vp[dz][dy][dx] = v.x;
                 vr[dz][dy][dx] = v.y;
               }
