@@ -210,6 +210,23 @@ def test_walls_interior_tiles_take_plain_pull(O, tiling):
     assert e["rho"] < TOL and e["rho_r"] < TOL and e["rho_b"] < TOL and e["u"] < TOL, e
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_walls_interior_tiles_half_storage(storage):
+    """The interior/frame split with 16-bit storage: the jet between free-slip lateral walls
+    gives bitwise the same state with 32 x 8 tiles (plain interior, reflecting frame) as with
+    64 x 4 tiles (all frame)."""
+    pb = _wall_jet()
+    log(f"[walls, interior tiles] {storage} 100x44x64 jet")
+    lat = lbm.Lattice(pb, storage=storage, tiling=(32, 8, 9))
+    ref_lat = lbm.Lattice(pb, storage=storage, tiling=(64, 4, 24))
+    lat.step(60)
+    ref_lat.step(60)
+    same = bool(np.array_equal(lat.populations(), ref_lat.populations()))
+    lat.close()
+    ref_lat.close()
+    assert same, "split and unsplit launches disagree"
+
+
 def test_autotune_keeps_state_and_results():
     """lbm_autotune times the tile shapes on a scratch lattice: the context's state is
     untouched, the chosen shape is a supported one, and the steps after it agree bit for bit
