@@ -2,8 +2,8 @@
 // build of the host side of the HIP library (include/lbm.h).  On a machine without a GPU it
 // runs every host-only path: parameter validation of lbm_create and lbm_batch_create, the
 // surface-tension conversions, the per-cell collision compiled for the host
-// (lbm_selftest_collide_host) on interface, bulk, zero- and tiny-gradient cells, error text
-// and NULL handling.  Exit status 0 when every call returns what it should.
+// (lbm_selftest_collide_host) on interface, bulk, zero- and tiny-gradient cells, the tile
+// cover of the step's launches (lbm_selftest_tile_sets_host), error text and NULL handling.  Exit status 0 when every call returns what it should.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -96,6 +96,27 @@ int main() {
       EXPECT(std::fabs(mr - r0) < 1e-6 && std::fabs(mb - b0) < 1e-6);
     }
   EXPECT(lbm_selftest_collide_host(nullptr, fr, fb, grads[0], grads[0], outr, outb) == LBM_EINVAL);
+
+  // tile cover of the step's launches, with and without lateral walls: every tile once
+  const int shapes[5][2] = {{32, 4}, {32, 8}, {64, 4}, {64, 8}, {32, 16}};
+  for (int walls = 0; walls < 2; ++walls)
+    for (const auto& sh : shapes) {
+      lbm_params q = base();
+      q.nx = 200; q.ny = 72;
+      if (walls) q.face[0] = q.face[1] = q.face[2] = q.face[3] = LBM_FREESLIP;
+      const int tx = (q.nx + sh[0] - 1) / sh[0], ty = (q.ny + sh[1] - 1) / sh[1], nt = tx * ty;
+      int counts[3 * 7 * 18];
+      EXPECT(3 * nt <= (int)(sizeof(counts) / sizeof(int)));
+      EXPECT(lbm_selftest_tile_sets_host(&q, sh[0], sh[1], counts) == LBM_OK);
+      for (int t = 0; t < nt; ++t) EXPECT(counts[t] + counts[nt + t] + counts[2 * nt + t] == 1);
+    }
+  {
+    lbm_params q = base();
+    int counts[3 * 64];
+    EXPECT(lbm_selftest_tile_sets_host(&q, 16, 16, counts) == LBM_EINVAL);
+    EXPECT(lbm_selftest_tile_sets_host(nullptr, 32, 8, counts) == LBM_EINVAL);
+    EXPECT(lbm_selftest_tile_sets_host(&q, 32, 8, nullptr) == LBM_EINVAL);
+  }
   std::printf("host sanitizer driver: %d failures\n", failures);
   return failures ? 1 : 0;
 }
