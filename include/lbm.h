@@ -104,10 +104,11 @@ lbm_status lbm_set_inflow(lbm_ctx *ctx, double xc, double yc, double diameter, d
 /* Tile shape of the step kernel: (tx, ty) in {(32, 4), (32, 8), (32, 16), (64, 4), (64, 8)}
  * cells per workgroup, zchunk >= 1 z planes per workgroup, or 0 to let the library choose
  * it from the number of workgroups the device holds at once.  Default: (64, 4, 0) for
- * nx >= 64 without lateral walls, (32, 8, 0) otherwise.  With free-slip x or y faces a step
- * is two launches, the interior tiles (no cell or ring cell on a wall) and the frame of wall
- * tiles; with zchunk = 0 each gets its own z chunk.  Results do not depend on the tiling;
- * this is a tuning hook.  LBM_EINVAL for other shapes or zchunk < 0. */
+ * nx >= 64, (32, 8, 0) otherwise.  With free-slip x or y faces a step is up to four
+ * launches: the interior tiles (no cell or ring cell on a wall), and the tiles on the x
+ * walls, on the y walls and at the corners; with zchunk = 0 each gets its own z chunk.
+ * Results do not depend on the tiling; this is a tuning hook.  LBM_EINVAL for other shapes
+ * or zchunk < 0. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int tx, int ty, int zchunk);
 
 /* Time each supported tile shape (32x8, 64x4, 32x4) for trial_steps steps on a scratch

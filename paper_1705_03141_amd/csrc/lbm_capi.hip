@@ -41,8 +41,8 @@ struct lbm_ctx {
   long long step = 0;
   bool initialised = false;
   int tx = 0, ty = 0, zchunk = 0;  // 0: chosen at the first step (choose_tiling, auto_zchunk)
-  int zchunk_in = 0, zchunk_fr = 0;  // with lateral walls and an automatic zchunk: the z chunks
-                                     // of the interior and the frame launch (0: zchunk)
+  int zchunk_set[5] = {0, 0, 0, 0, 0};  // with lateral walls and an automatic zchunk: the z
+                                        // chunk of each tile set's launch (0: zchunk)
   bool in_batch = false;           // advanced only by lbm_batch_step
   bool frozen = false;             // a batch case found unstable: no longer stepped
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -277,7 +277,7 @@ extern "C" lbm_status lbm_set_tiling(lbm_ctx* c, int tx, int ty, int zchunk) {
   c->tx = tx;
   c->ty = ty;
   c->zchunk = zchunk;
-  c->zchunk_in = c->zchunk_fr = 0;
+  for (int& z : c->zchunk_set) z = 0;
   return LBM_OK;
 }
 
@@ -357,26 +357,25 @@ static void fill_step_args(const lbm_ctx* c, int cur, int out_cur, StepArgs& s);
 
 static void choose_tiling(lbm_ctx* c) {
   if (c->tx == 0) {
-    // measured on MI355X: 64 x 4 tiles on rows of 64 cells or more, 32 x 8 otherwise and with
-    // lateral walls, where narrower tiles leave fewer tiles in the frame that takes the
-    // reflecting instance (jet 256x256x1024 between walls: 6.45 against 6.63 ms per step)
+    // measured on MI355X: 64 x 4 tiles on rows of 64 cells or more, 32 x 8 otherwise; with
+    // lateral walls 64 x 4 and 32 x 8 are within 0.3 % of each other on the jet
     // (lbm_autotune times the shapes for a given lattice)
-    const bool wide = c->geo.nx >= 64 && !(c->geo.wall_x || c->geo.wall_y);
+    const bool wide = c->geo.nx >= 64;
     c->tx = wide ? 64 : 32;
     c->ty = wide ? 4 : 8;
   }
   if (c->zchunk < 1) {
     c->zchunk = auto_zchunk(c);
-    c->zchunk_in = c->zchunk_fr = 0;
+    for (int& z : c->zchunk_set) z = 0;
     if (c->geo.wall_x || c->geo.wall_y) {
-      // the interior and the frame run as two launches, one after the other: each is chunked
-      // in z to fill the device by itself
+      // the interior and the parts of the frame run as launches one after the other: each is
+      // chunked in z to fill the device by itself
       StepArgs s{};
       fill_step_args(c, 0, 0, s);
-      s.tile_set = kInteriorTiles;
-      c->zchunk_in = zchunk_for(c, tiles_in_set(s));
-      s.tile_set = kFrameTiles;
-      c->zchunk_fr = zchunk_for(c, tiles_in_set(s));
+      for (int set = kInteriorTiles; set <= kCorners; ++set) {
+        s.tile_set = set;
+        c->zchunk_set[set] = zchunk_for(c, tiles_in_set(s));
+      }
     }
   }
 }
@@ -447,15 +446,14 @@ static lbm_status enqueue_one(lbm_ctx* c) {
   fill_step_args(c, c->cur, c->out_cur, s);
   hipError_t e = hipSuccess;
   if (G.wall_x || G.wall_y) {
-    // the interior tiles with the plain pull, the frame with the reflecting instance
-    if (s.tx_hi > s.tx_lo) {
-      s.tile_set = kInteriorTiles;
-      set_zchunk(G, c->zchunk_in > 0 ? c->zchunk_in : c->zchunk, s);
+    // the interior tiles with the plain pull, the x edges, y edges and corners of the frame
+    // with the instances that reflect at those walls
+    for (int set = kInteriorTiles; set <= kCorners && e == hipSuccess; ++set) {
+      s.tile_set = set;
+      if (tiles_in_set(s) == 0) continue;
+      set_zchunk(G, c->zchunk_set[set] > 0 ? c->zchunk_set[set] : c->zchunk, s);
       e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
     }
-    s.tile_set = kFrameTiles;
-    set_zchunk(G, c->zchunk_fr > 0 ? c->zchunk_fr : c->zchunk, s);
-    if (e == hipSuccess) e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
   } else {
     e = launch_step((int)c->p.storage, s, c->tx, c->ty, c->stream);
   }
@@ -719,7 +717,7 @@ extern "C" lbm_status lbm_load_state(lbm_ctx* c, const void* src, size_t bytes) 
 // lbm_batch_step call.
 struct BatchGroup {
   int storage = 0, tx = 0, ty = 0;
-  bool lat = false;                     // lateral free-slip walls (a separate kernel instance)
+  int lat = 0;                          // reflection mode of the instance (lat_mode_of)
   int tile_set = kAllTiles;             // the tiles of each case the group's launch covers
   std::vector<int> cases;               // indices into lbm_batch::c
   StepArgs* d_args[2] = {nullptr, nullptr};  // device tables for parity 0 and 1
@@ -841,7 +839,7 @@ static void batch_tiling(lbm_batch* b) {
 
 static lbm_status build_groups(lbm_batch* b) {
   free_groups(b);
-  auto add = [&](int k, bool lat, int set) {
+  auto add = [&](int k, int lat, int set) {
     const lbm_ctx* c = b->c[k];
     BatchGroup* g = nullptr;
     for (auto& x : b->groups)
@@ -861,13 +859,16 @@ static lbm_status build_groups(lbm_batch* b) {
     const lbm_ctx* c = b->c[k];
     if (c->frozen) continue;
     if (c->geo.wall_x || c->geo.wall_y) {
-      // with lateral walls: the interior tiles in a plain group, the frame in a reflecting one
+      // with lateral walls: the interior tiles in a plain group, each part of the frame in the
+      // group of its reflection mode
       StepArgs s{};
       fill_step_args(c, 0, 0, s);
-      if (s.tx_hi > s.tx_lo) add(k, false, kInteriorTiles);
-      add(k, true, kFrameTiles);
+      for (int set = kInteriorTiles; set <= kCorners; ++set) {
+        s.tile_set = set;
+        if (tiles_in_set(s) > 0) add(k, lat_mode_of(set, true), set);
+      }
     } else {
-      add(k, false, kAllTiles);
+      add(k, 0, kAllTiles);
     }
   }
   for (auto& g : b->groups) {
@@ -1161,16 +1162,23 @@ extern "C" lbm_status lbm_selftest_tile_sets_host(const lbm_params* params, int 
   const int nt = s.tiles_x * s.tiles_y;
   for (int k = 0; k < 3 * nt; ++k) counts[k] = 0;
   const bool walls = tmp.geo.wall_x || tmp.geo.wall_y;
-  const int sets[3] = {kAllTiles, kInteriorTiles, kFrameTiles};
-  for (int b = 0; b < 3; ++b) {
-    // the launches enqueue_one makes: one over all tiles without walls, else interior + frame
-    if ((sets[b] == kAllTiles) == walls) continue;
-    s.tile_set = sets[b];
+  // the launches enqueue_one makes: one over all tiles without walls, else the interior and
+  // the x edges, y edges and corners of the frame (reported together as the frame)
+  for (int set = kAllTiles; set <= kCorners; ++set) {
+    if ((set == kAllTiles) == walls) continue;
+    const int b = set == kAllTiles ? 0 : (set == kInteriorTiles ? 1 : 2);
+    s.tile_set = set;
     const int n = tiles_in_set(s);
     for (int t = 0; t < n; ++t) {
       int i = -1, j = -1;
       tile_of(s, t, i, j);
       if (i < 0 || i >= s.tiles_x || j < 0 || j >= s.tiles_y) return fail(nullptr, LBM_EDEVICE, "tile out of range");
+      // a frame tile of an x edge or a y edge touches the walls of that axis only
+      const int x0 = i * tx, y0 = j * ty;
+      const bool on_x = tmp.geo.wall_x && (x0 == 0 || x0 + tx > tmp.geo.nx - 2);
+      const bool on_y = tmp.geo.wall_y && (y0 == 0 || y0 + ty > tmp.geo.ny - 2);
+      if ((set == kFrameX && on_y) || (set == kFrameY && on_x) || (set == kInteriorTiles && (on_x || on_y)))
+        return fail(nullptr, LBM_EDEVICE, "tile in the wrong set");
       counts[b * nt + j * s.tiles_x + i]++;
     }
   }

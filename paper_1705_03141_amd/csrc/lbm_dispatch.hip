@@ -18,7 +18,7 @@ hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream
 }
 
 hipError_t launch_batch(int storage, const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
-                        int tx, int ty, bool lat, hipStream_t s) {
+                        int tx, int ty, int lat, hipStream_t s) {
   switch (storage) {
     case 0: return launch_batch_T<float>(cases, first, ncases, nblocks, init, tx, ty, lat, s);
     case 1: return launch_batch_T<_Float16>(cases, first, ncases, nblocks, init, tx, ty, lat, s);

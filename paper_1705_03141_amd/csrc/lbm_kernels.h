@@ -31,7 +31,7 @@ struct StepArgs {
   long long step;
   int init_mode;
   int zchunk, tiles_x, tiles_y, nchunks;
-  int tile_set;          // kAllTiles, kInteriorTiles or kFrameTiles
+  int tile_set;          // a TileSet value
   int tx_lo, tx_hi, ty_lo, ty_hi;  // the interior rectangle of tiles [tx_lo, tx_hi) x [ty_lo, ty_hi)
   int* unstable;         // set to 1 by a cell whose density is NaN, infinite or <= 0
   int skip_unstable;     // 1: workgroups of a flagged lattice return at once (batches)
@@ -42,43 +42,57 @@ struct StepArgs {
 };
 
 // The tiles one launch of the step kernel covers.  With lateral walls the tiles whose cells
-// and ring cells are all off the walls (the interior rectangle) take the plain pull, and only
-// the frame of tiles around it the instance that reflects at the walls.
-enum TileSet { kAllTiles = 0, kInteriorTiles = 1, kFrameTiles = 2 };
+// and ring cells are all off the walls (the interior rectangle) take the plain pull.  The
+// frame around it is split by the walls its tiles touch: the x edges (tiles left and right
+// of the rectangle, in its rows), the y edges (above and below it, in its columns) and the
+// corners; each takes the instance that reflects at those walls only.
+enum TileSet { kAllTiles = 0, kInteriorTiles = 1, kFrameX = 2, kFrameY = 3, kCorners = 4 };
 
-__host__ __device__ inline int tiles_in_set(const StepArgs& a) {
-  const int all = a.tiles_x * a.tiles_y, inner = (a.tx_hi - a.tx_lo) * (a.ty_hi - a.ty_lo);
-  return a.tile_set == kAllTiles ? all : (a.tile_set == kInteriorTiles ? inner : all - inner);
+// Reflection mode of the step kernel instance for a tile set: bit 0 x walls, bit 1 y walls.
+__host__ __device__ inline int lat_mode_of(int tile_set, bool walls) {
+  if (!walls || tile_set == kInteriorTiles) return 0;
+  return tile_set == kFrameX ? 1 : (tile_set == kFrameY ? 2 : 3);
 }
 
-// Tile (txi, tyi) of the t-th tile of the launch's set.  The frame is numbered by bands: the
-// rows below the rectangle, the rows above it, then the side pieces of its rows.
+__host__ __device__ inline int tiles_in_set(const StepArgs& a) {
+  const int w_in = a.tx_hi - a.tx_lo, h_in = a.ty_hi - a.ty_lo;
+  const int side = a.tx_lo + (a.tiles_x - a.tx_hi), rows_out = a.ty_lo + (a.tiles_y - a.ty_hi);
+  switch (a.tile_set) {
+    case kInteriorTiles: return w_in * h_in;
+    case kFrameX: return side * h_in;
+    case kFrameY: return w_in * rows_out;
+    case kCorners: return side * rows_out;
+    default: return a.tiles_x * a.tiles_y;
+  }
+}
+
+// Tile (txi, tyi) of the t-th tile of the launch's set (row by row within the set).
 __host__ __device__ inline void tile_of(const StepArgs& a, int t, int& txi, int& tyi) {
-  if (a.tile_set == kInteriorTiles) {
-    const int w = a.tx_hi - a.tx_lo;
-    tyi = a.ty_lo + t / w;
-    txi = a.tx_lo + t % w;
-    return;
-  }
-  if (a.tile_set == kFrameTiles) {
-    const int below = a.ty_lo * a.tiles_x, above = (a.tiles_y - a.ty_hi) * a.tiles_x;
-    if (t >= below && t < below + above) {
-      t -= below;
-      tyi = a.ty_hi + t / a.tiles_x;
-      txi = t % a.tiles_x;
+  const int w_in = a.tx_hi - a.tx_lo, side = a.tx_lo + (a.tiles_x - a.tx_hi);
+  // the k-th column index left or right of the rectangle, and the r-th row above or below it
+  auto side_col = [&](int k) { return k < a.tx_lo ? k : a.tx_hi + (k - a.tx_lo); };
+  auto out_row = [&](int r) { return r < a.ty_lo ? r : a.ty_hi + (r - a.ty_lo); };
+  switch (a.tile_set) {
+    case kInteriorTiles:
+      tyi = a.ty_lo + t / w_in;
+      txi = a.tx_lo + t % w_in;
       return;
-    }
-    if (t >= below + above) {
-      t -= below + above;
-      const int side = a.tx_lo + (a.tiles_x - a.tx_hi);
+    case kFrameX:
       tyi = a.ty_lo + t / side;
-      const int k = t % side;
-      txi = k < a.tx_lo ? k : a.tx_hi + (k - a.tx_lo);
+      txi = side_col(t % side);
       return;
-    }
+    case kFrameY:
+      tyi = out_row(t / w_in);
+      txi = a.tx_lo + t % w_in;
+      return;
+    case kCorners:
+      tyi = out_row(t / side);
+      txi = side_col(t % side);
+      return;
+    default:
+      tyi = t / a.tiles_x;
+      txi = t - tyi * a.tiles_x;
   }
-  tyi = t / a.tiles_x;
-  txi = t - tyi * a.tiles_x;
 }
 
 // Arguments of the outlet and read-back kernels.
@@ -106,7 +120,7 @@ template <typename T>
 hipError_t launch_inflow_T(const StepArgs& a, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_T(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int tx, int ty,
-                          bool lat, hipStream_t s);
+                          int lat, hipStream_t s);
 template <typename T>
 int step_resident_blocks_T(int tx, int ty, int device);
 template <typename T>
@@ -134,7 +148,7 @@ hipError_t launch_step(int storage, const StepArgs& a, int tx, int ty, hipStream
 // all with the same storage, tile shape and lateral rule: lat = free-slip x or y walls),
 // first (device, ncases + 1 block offsets, each a multiple of 8), nblocks = first[ncases].
 hipError_t launch_batch(int storage, const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
-                        int tx, int ty, bool lat, hipStream_t s);
+                        int tx, int ty, int lat, hipStream_t s);
 // Inflow sites of plane z = 0 written into the step's output state (after launch_step).
 hipError_t launch_inflow(int storage, const StepArgs& a, hipStream_t s);
 // Workgroups of the step kernel that fit on the device at once (0 if unknown).

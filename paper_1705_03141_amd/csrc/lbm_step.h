@@ -117,28 +117,37 @@ __device__ __forceinline__ void column_offsets(const Geo& G, int x, int y, unsig
 }
 
 // Lateral reflection of a source offset at a cell with wall flags wf (wall_flags): true where
-// the source (dx, dy) lies beyond a free-slip wall in x (AXIS 0) or y (AXIS 1).
-template <int AXIS, int D>
+// the source (dx, dy) lies beyond a free-slip wall in x (AXIS 0) or y (AXIS 1).  LAT is the
+// instance's reflection mode (bit 0: x walls, bit 1: y walls); an axis it leaves out never
+// reflects.
+template <int AXIS, int D, int LAT>
 __device__ __forceinline__ bool reflects(int wf) {
-  if constexpr (D == 0) return false;
+  if constexpr (D == 0 || (LAT & (1 << AXIS)) == 0) return false;
   constexpr int bit = (AXIS == 0 ? 0 : 2) + (D < 0 ? 0 : 1);
   return (wf >> bit) & 1;
 }
 
+// Whether direction i of a pull can reflect at a lateral wall in reflection mode LAT.
+template <int LAT, int DX, int DY>
+constexpr bool lat_dir() {
+  return ((LAT & 1) && DX != 0) || ((LAT & 2) && DY != 0);
+}
+
 // Issue the 27 population loads of a pull in mode MODE.  slab[k] covers the 27 population
 // planes of source plane z - 1 + k; the raw word of direction i is left in ld[i].  With
-// lateral walls (LAT) a source beyond a wall is the boundary cell and the mirrored population
-// (reading R9), chosen per lane: its population plane then enters the per-lane offset.
-template <typename T, int MODE, bool LAT>
+// lateral walls (LAT != 0) a source beyond a wall is the boundary cell and the mirrored
+// population (reading R9), chosen per lane: its population plane then enters the per-lane
+// offset.
+template <typename T, int MODE, int LAT>
 __device__ __forceinline__ void issue_pull(const rsrc_t (&slab)[3], int plane_bytes, const unsigned (&o)[3][3], int wf,
                                            typename Word<T>::W (&ld)[Q]) {
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     constexpr Src s = resolve<i, MODE>();
-    if constexpr (!LAT || (s.dx == 0 && s.dy == 0)) {
+    if constexpr (!lat_dir<LAT, s.dx, s.dy>()) {
       ld[i] = Word<T>::load(slab[s.dz + 1], o[s.dy + 1][s.dx + 1], s.j * plane_bytes);
     } else {
-      const bool rx = reflects<0, s.dx>(wf), ry = reflects<1, s.dy>(wf);
+      const bool rx = reflects<0, s.dx, LAT>(wf), ry = reflects<1, s.dy, LAT>(wf);
       constexpr int jx = mirror_x(s.j), jy = mirror_y(s.j), jxy = mirror_x(mirror_y(s.j));
       const unsigned col = rx ? (ry ? o[1][1] : o[s.dy + 1][1]) : (ry ? o[1][s.dx + 1] : o[s.dy + 1][s.dx + 1]);
       const int j = rx ? (ry ? jxy : jx) : (ry ? jy : s.j);
@@ -165,7 +174,7 @@ __device__ __forceinline__ float div_nc(float a, float b) {
   return a / b;
 }
 
-template <typename T, int MODE, bool WANT_DF, int SX, bool LAT>
+template <typename T, int MODE, bool WANT_DF, int SX, int LAT>
 __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], const float4* const (&S)[3], const float2* const (&W)[3],
                                             int idx0, int wf, const PullConst& C, float& rho, float& rho_r, float& rho_b,
                                             float& e_new, float (&df)[Q], float& shift_out, float& drho_out) {
@@ -194,14 +203,14 @@ __device__ __forceinline__ void finish_pull(const typename Word<T>::W (&ld)[Q], 
     constexpr int off = (s.dy + 1) * SX + s.dx + 1;
     constexpr int sh = shell_of(i);
     constexpr bool self_src = s.dx == 0 && s.dy == 0 && s.dz == 0;  // bounce-back
-    constexpr bool lat = LAT && (s.dx != 0 || s.dy != 0);
+    constexpr bool lat = lat_dir<LAT, s.dx, s.dy>();
     // lateral wall: the source is the boundary cell along a reflected axis, and the velocity
     // component normal to that wall is reversed
     bool rx = false, ry = false;
     int offl = off;
     if constexpr (lat) {
-      rx = reflects<0, s.dx>(wf);
-      ry = reflects<1, s.dy>(wf);
+      rx = reflects<0, s.dx, LAT>(wf);
+      ry = reflects<1, s.dy, LAT>(wf);
       offl = ((ry ? 0 : s.dy) + 1) * SX + (rx ? 0 : s.dx) + 1;
     }
     const float4 src = S[s.dz + 1][idx0 + offl];
@@ -288,7 +297,7 @@ struct PlaneState {
   }
 };
 
-template <typename T, int TX, int TY, bool INIT, bool LAT>
+template <typename T, int TX, int TY, bool INIT, int LAT>
 #ifndef LBM_STEP_WAVES_PER_EU
 #define LBM_STEP_WAVES_PER_EU 2
 #endif
@@ -316,11 +325,10 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   // Issue order of a pass's loads (measured): with FP32 populations the staged scalars go
   // first, with 16-bit populations after the population loads.  Their LDS write waits until
   // the pull is complete, so that the pull consumes each population load as soon as it and
-  // the older loads have arrived, rather than after all of them.  The lateral-wall instance,
-  // which spills, keeps the scalars first and their LDS write before the pull (10 % faster
-  // there).
-  constexpr bool kStoreLate = !LAT;
-  constexpr bool kStageFirst = LAT || sizeof(T) == 4;
+  // the older loads have arrived, rather than after all of them.  The corner instance (x and
+  // y walls), which spills, keeps the scalars first and their LDS write before the pull.
+  constexpr bool kStoreLate = LAT != 3;
+  constexpr bool kStageFirst = LAT == 3 || sizeof(T) == 4;
 
   const Geo& G = A.geo;
   const bool zper = G.face_lo == FACE_PERIODIC;
@@ -361,7 +369,9 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   const int rcol = rgy * G.nx + rgx;
   const int sR = (ry + 2) * SX + rx + 2, dR = (ry + 1) * DX + rx + 1;
   // lateral wall flags of the own and the ring cell (0 without lateral walls)
-  const int wfI = LAT ? wall_flags(G, gx, gy) : 0, wfR = LAT ? wall_flags(G, rgx, rgy) : 0;
+  // (only the walls of the instance's mode: the tiles it serves touch no others)
+  constexpr int kWallMask = ((LAT & 1) ? 3 : 0) | ((LAT & 2) ? 12 : 0);
+  const int wfI = LAT ? wall_flags(G, gx, gy) & kWallMask : 0, wfR = LAT ? wall_flags(G, rgx, rgy) & kWallMask : 0;
   // staged cells
   unsigned stOff[KS];  // byte offsets in a scalar plane
 #pragma unroll
@@ -576,14 +586,14 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   if (bad) *A.unstable = 1;
 }
 
-template <typename T, int TX, int TY, bool INIT, bool LAT>
+template <typename T, int TX, int TY, bool INIT, int LAT>
 __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU) step_kernel(const StepArgs A) {
   step_body<T, TX, TY, INIT, LAT>(A, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Many lattices in one launch: case c owns blocks [first[c], first[c+1]) of the grid, each
 // range padded to a multiple of 8 blocks so that the XCD-aware numbering holds per case.
-template <typename T, int TX, int TY, bool INIT, bool LAT>
+template <typename T, int TX, int TY, bool INIT, int LAT>
 __global__ void __launch_bounds__(TX * TY, LBM_STEP_WAVES_PER_EU)
     batch_step_kernel(const StepArgs* __restrict__ cases, const int* __restrict__ first, int ncases) {
   const int b = (int)blockIdx.x;
@@ -645,7 +655,7 @@ __global__ void __launch_bounds__(256)
 }
 
 // ================================================================== launchers
-template <typename T, int TX, int TY, bool LAT>
+template <typename T, int TX, int TY, int LAT>
 hipError_t launch_step_lat(const StepArgs& a, hipStream_t s) {
   const long long blocks = (long long)tiles_in_set(a) * a.nchunks;
   if (blocks == 0) return hipSuccess;
@@ -656,15 +666,20 @@ hipError_t launch_step_lat(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The step kernel with lateral free-slip walls is a separate instance: lattices with periodic
+// The step kernel with lateral free-slip walls comes in instances that reflect at x walls, y
+// walls or both, each for the frame tiles that touch those walls; lattices with periodic
 // sides, and the interior tiles of a lattice with walls, keep the plain pull.
 template <typename T, int TX, int TY>
 hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
-  return ((a.geo.wall_x || a.geo.wall_y) && a.tile_set != kInteriorTiles) ? launch_step_lat<T, TX, TY, true>(a, s)
-                                                                          : launch_step_lat<T, TX, TY, false>(a, s);
+  switch (lat_mode_of(a.tile_set, a.geo.wall_x || a.geo.wall_y)) {
+    case 1: return launch_step_lat<T, TX, TY, 1>(a, s);
+    case 2: return launch_step_lat<T, TX, TY, 2>(a, s);
+    case 3: return launch_step_lat<T, TX, TY, 3>(a, s);
+    default: return launch_step_lat<T, TX, TY, 0>(a, s);
+  }
 }
 
-template <typename T, int TX, int TY, bool LAT>
+template <typename T, int TX, int TY, int LAT>
 hipError_t launch_batch_lat(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init,
                             hipStream_t s) {
   if (init)
@@ -677,15 +692,19 @@ hipError_t launch_batch_lat(const StepArgs* cases, const int* first, int ncases,
 }
 
 template <typename T, int TX, int TY>
-hipError_t launch_batch_tile(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, bool lat,
+hipError_t launch_batch_tile(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int lat,
                              hipStream_t s) {
-  return lat ? launch_batch_lat<T, TX, TY, true>(cases, first, ncases, nblocks, init, s)
-             : launch_batch_lat<T, TX, TY, false>(cases, first, ncases, nblocks, init, s);
+  switch (lat) {
+    case 1: return launch_batch_lat<T, TX, TY, 1>(cases, first, ncases, nblocks, init, s);
+    case 2: return launch_batch_lat<T, TX, TY, 2>(cases, first, ncases, nblocks, init, s);
+    case 3: return launch_batch_lat<T, TX, TY, 3>(cases, first, ncases, nblocks, init, s);
+    default: return launch_batch_lat<T, TX, TY, 0>(cases, first, ncases, nblocks, init, s);
+  }
 }
 
 template <typename T>
 hipError_t launch_batch_T(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int tx, int ty,
-                          bool lat, hipStream_t s) {
+                          int lat, hipStream_t s) {
   if (tx == 32 && ty == 4) return launch_batch_tile<T, 32, 4>(cases, first, ncases, nblocks, init, lat, s);
   if (tx == 32 && ty == 8) return launch_batch_tile<T, 32, 8>(cases, first, ncases, nblocks, init, lat, s);
   if (tx == 64 && ty == 4) return launch_batch_tile<T, 64, 4>(cases, first, ncases, nblocks, init, lat, s);
@@ -739,7 +758,7 @@ int step_resident_blocks_T(int tx, int ty, int device) {
 
 #define LBM_INSTANTIATE_STEP(T)                                                 \
   template hipError_t launch_step_T<T>(const StepArgs&, int, int, hipStream_t); \
-  template hipError_t launch_batch_T<T>(const StepArgs*, const int*, int, int, bool, int, int, bool, hipStream_t); \
+  template hipError_t launch_batch_T<T>(const StepArgs*, const int*, int, int, bool, int, int, int, hipStream_t); \
   template hipError_t launch_inflow_T<T>(const StepArgs&, hipStream_t);                                         \
   template hipError_t launch_batch_inflow_T<T>(const StepArgs*, const int*, int, int, long long, hipStream_t);          \
   template int step_resident_blocks_T<T>(int, int, int);
