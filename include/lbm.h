@@ -254,7 +254,10 @@ lbm_status lbm_selftest_collide_host(const lbm_params *params, const double *fr,
  * over all tiles (block 0), over the interior tiles (block 1) and over the frame tiles (block 2)
  * would process it.  Without lateral walls one launch covers all tiles; with free-slip x or y
  * faces the interior tiles (none of whose cells or ring cells lies on a wall) take the plain
- * pull and the frame the reflecting instance.  LBM_EINVAL for invalid parameters or shapes. */
+ * pull, and the frame is three launches (the x edges, the y edges and the corners) with the
+ * instances that reflect at those walls.  LBM_EDEVICE if a tile falls outside the lattice or
+ * into a set whose walls it does not touch (an internal error); LBM_EINVAL for invalid
+ * parameters or shapes. */
 lbm_status lbm_selftest_tile_sets_host(const lbm_params *params, int tx, int ty, int *counts);
 
 #ifdef __cplusplus
