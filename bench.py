@@ -3,7 +3,9 @@
 Workload (default): the liquid jet on 256 x 256 x 1024 (D = 16 inflow disk with 1 % noise,
 u = 0.04, gamma 1.6, nu 1.8e-4, We 220, Fr 8.5, free-slip inlet plane, convective outflow,
 periodic sides), the largest single-GPU configuration the throughput metric is quoted on;
-``--workload rt`` runs the Rayleigh-Taylor problem on 128 x 128 x 512 instead.  FP32
+``--workload rt`` runs the Rayleigh-Taylor problem on 128 x 128 x 512 instead, and
+``--workload jet_walls`` the same jet between free-slip lateral walls (the paper's set-up, a
+step of up to four launches: interior tiles and the frame along the walls).  FP32
 populations and arithmetic.  A "step" is one full time step of the method over the whole
 lattice (outlet plane, fused step kernel, inflow plane).  Prints one JSON line:
 
@@ -386,8 +388,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--sweep-storage", default="f16", choices=["f32", "f16", "bf16"],
                     help="population storage of --sweep (the sweep is specified in FP16)")
-    ap.add_argument("--workload", default="jet", choices=["rt", "jet"],
-                    help="jet: the liquid jet 256 x 256 x 1024 (the default); rt: Rayleigh-Taylor 128 x 128 x 512")
+    ap.add_argument("--workload", default="jet", choices=["rt", "jet", "jet_walls"],
+                    help="jet: the liquid jet 256 x 256 x 1024 (the default); rt: Rayleigh-Taylor 128 x 128 x 512; "
+                         "jet_walls: the jet between free-slip lateral walls")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16/BF16-storage runs")
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first (lbm_autotune) instead of using the default 64 x 4")
@@ -432,7 +435,7 @@ def main():
 
     from paper_1705_03141_amd import workloads as W
 
-    pb = W.cfg_rayleigh_taylor() if args.workload == "rt" else W.cfg_jet()
+    pb = {"rt": W.cfg_rayleigh_taylor, "jet": W.cfg_jet, "jet_walls": W.cfg_jet_walls}[args.workload]()
     n = pb.ncells
     log(f"{pb.name} {pb.nx}x{pb.ny}x{pb.nz}, storage {args.storage}, {args.warmup}+{args.steps} steps")
     wall, kernel_ms, diag = run_gpu(pb, args.storage, args.steps, args.warmup, args.autotune)

@@ -104,9 +104,10 @@ lbm_status lbm_set_inflow(lbm_ctx *ctx, double xc, double yc, double diameter, d
 /* Tile shape of the step kernel: (tx, ty) in {(32, 4), (32, 8), (32, 16), (64, 4), (64, 8)}
  * cells per workgroup, zchunk >= 1 z planes per workgroup, or 0 to let the library choose
  * it from the number of workgroups the device holds at once.  Default: (64, 4, 0) for
- * nx >= 64, (32, 8, 0) otherwise.  With free-slip x or y faces a step is up to four
- * launches: the interior tiles (no cell or ring cell on a wall), and the tiles on the x
- * walls, on the y walls and at the corners; with zchunk = 0 each gets its own z chunk.
+ * nx >= 64, (32, 8, 0) otherwise.  With free-slip x or y faces a step is several launches:
+ * the interior tiles (no cell or ring cell on a wall), the tiles along the x walls and along
+ * the y walls (with FP16 storage: along each of the -x, +x, -y and +y walls), and the
+ * corners; with zchunk = 0 each gets its own z chunk.
  * Results do not depend on the tiling; this is a tuning hook.  LBM_EINVAL for other shapes
  * or zchunk < 0. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int tx, int ty, int zchunk);
@@ -193,8 +194,10 @@ typedef struct {
 } lbm_diag;
 lbm_status lbm_diagnostics(lbm_ctx *ctx, double xc, double yc, double zc, double r_in, double r_out, lbm_diag *out);
 
-/* Average duration in milliseconds of the step kernel over the last lbm_step call,
- * measured with HIP events on the context's stream (0 if none). */
+/* Average duration in milliseconds of one step's kernels over the last lbm_step call,
+ * measured with HIP events on the context's stream around the whole call (0 if none): the
+ * step kernel's launches and, where the lattice has them, the small outlet and inflow
+ * kernels. */
 double lbm_last_step_kernel_ms(const lbm_ctx *ctx);
 
 /* Human-readable text of the last error on ctx (or of the last failed lbm_create when ctx
@@ -254,10 +257,11 @@ lbm_status lbm_selftest_collide_host(const lbm_params *params, const double *fr,
  * over all tiles (block 0), over the interior tiles (block 1) and over the frame tiles (block 2)
  * would process it.  Without lateral walls one launch covers all tiles; with free-slip x or y
  * faces the interior tiles (none of whose cells or ring cells lies on a wall) take the plain
- * pull, and the frame is three launches (the x edges, the y edges and the corners) with the
- * instances that reflect at those walls.  LBM_EDEVICE if a tile falls outside the lattice or
- * into a set whose walls it does not touch (an internal error); LBM_EINVAL for invalid
- * parameters or shapes. */
+ * pull, and the frame is up to three launches (x edges, y edges, corners), five with FP16
+ * storage (one per wall along the edges, one for the corners), with the instances that
+ * reflect at those walls.  LBM_EDEVICE if a tile falls
+ * outside the lattice or touches a wall its launch does not reflect at (an internal error);
+ * LBM_EINVAL for invalid parameters or shapes. */
 lbm_status lbm_selftest_tile_sets_host(const lbm_params *params, int tx, int ty, int *counts);
 
 #ifdef __cplusplus

@@ -41,8 +41,8 @@ struct lbm_ctx {
   long long step = 0;
   bool initialised = false;
   int tx = 0, ty = 0, zchunk = 0;  // 0: chosen at the first step (choose_tiling, auto_zchunk)
-  int zchunk_set[5] = {0, 0, 0, 0, 0};  // with lateral walls and an automatic zchunk: the z
-                                        // chunk of each tile set's launch (0: zchunk)
+  int zchunk_set[kCorners + 1] = {};  // with lateral walls and an automatic zchunk: the z
+                                      // chunk of each tile set's launch (0: zchunk)
   bool in_batch = false;           // advanced only by lbm_batch_step
   bool frozen = false;             // a batch case found unstable: no longer stepped
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -372,9 +372,11 @@ static void choose_tiling(lbm_ctx* c) {
       // chunked in z to fill the device by itself
       StepArgs s{};
       fill_step_args(c, 0, 0, s);
-      for (int set = kInteriorTiles; set <= kCorners; ++set) {
-        s.tile_set = set;
-        c->zchunk_set[set] = zchunk_for(c, tiles_in_set(s));
+      int sets[kCorners + 1];
+      const int nsets = wall_tile_sets((int)c->p.storage, sets);
+      for (int k = 0; k < nsets; ++k) {
+        s.tile_set = sets[k];
+        c->zchunk_set[sets[k]] = zchunk_for(c, tiles_in_set(s));
       }
     }
   }
@@ -446,9 +448,12 @@ static lbm_status enqueue_one(lbm_ctx* c) {
   fill_step_args(c, c->cur, c->out_cur, s);
   hipError_t e = hipSuccess;
   if (G.wall_x || G.wall_y) {
-    // the interior tiles with the plain pull, the x edges, y edges and corners of the frame
-    // with the instances that reflect at those walls
-    for (int set = kInteriorTiles; set <= kCorners && e == hipSuccess; ++set) {
+    // the interior tiles with the plain pull, the edges and corners of the frame with the
+    // instances that reflect at their walls
+    int sets[kCorners + 1];
+    const int nsets = wall_tile_sets((int)c->p.storage, sets);
+    for (int k = 0; k < nsets && e == hipSuccess; ++k) {
+      const int set = sets[k];
       s.tile_set = set;
       if (tiles_in_set(s) == 0) continue;
       set_zchunk(G, c->zchunk_set[set] > 0 ? c->zchunk_set[set] : c->zchunk, s);
@@ -863,9 +868,11 @@ static lbm_status build_groups(lbm_batch* b) {
       // group of its reflection mode
       StepArgs s{};
       fill_step_args(c, 0, 0, s);
-      for (int set = kInteriorTiles; set <= kCorners; ++set) {
-        s.tile_set = set;
-        if (tiles_in_set(s) > 0) add(k, lat_mode_of(set, true), set);
+      int sets[kCorners + 1];
+      const int nsets = wall_tile_sets((int)c->p.storage, sets);
+      for (int m = 0; m < nsets; ++m) {
+        s.tile_set = sets[m];
+        if (tiles_in_set(s) > 0) add(k, lat_mode_of(sets[m], true), sets[m]);
       }
     } else {
       add(k, 0, kAllTiles);
@@ -1163,9 +1170,12 @@ extern "C" lbm_status lbm_selftest_tile_sets_host(const lbm_params* params, int 
   for (int k = 0; k < 3 * nt; ++k) counts[k] = 0;
   const bool walls = tmp.geo.wall_x || tmp.geo.wall_y;
   // the launches enqueue_one makes: one over all tiles without walls, else the interior and
-  // the x edges, y edges and corners of the frame (reported together as the frame)
-  for (int set = kAllTiles; set <= kCorners; ++set) {
-    if ((set == kAllTiles) == walls) continue;
+  // the edges and corners of the frame for the storage type (reported together as the frame)
+  int sets[kCorners + 1];
+  const int nsets = walls ? wall_tile_sets((int)tmp.p.storage, sets) : 1;
+  if (!walls) sets[0] = kAllTiles;
+  for (int m = 0; m < nsets; ++m) {
+    const int set = sets[m];
     const int b = set == kAllTiles ? 0 : (set == kInteriorTiles ? 1 : 2);
     s.tile_set = set;
     const int n = tiles_in_set(s);
@@ -1173,12 +1183,14 @@ extern "C" lbm_status lbm_selftest_tile_sets_host(const lbm_params* params, int 
       int i = -1, j = -1;
       tile_of(s, t, i, j);
       if (i < 0 || i >= s.tiles_x || j < 0 || j >= s.tiles_y) return fail(nullptr, LBM_EDEVICE, "tile out of range");
-      // a frame tile of an x edge or a y edge touches the walls of that axis only
+      // the walls (bits of wall_flags) that the tile's cells, and its ring cells inside the
+      // lattice, lie on must be among those its instance reflects at (a ring cell beyond a
+      // wall, wrapped to the opposite side, is never read: there the stencil takes the
+      // boundary cell)
       const int x0 = i * tx, y0 = j * ty;
-      const bool on_x = tmp.geo.wall_x && (x0 == 0 || x0 + tx > tmp.geo.nx - 2);
-      const bool on_y = tmp.geo.wall_y && (y0 == 0 || y0 + ty > tmp.geo.ny - 2);
-      if ((set == kFrameX && on_y) || (set == kFrameY && on_x) || (set == kInteriorTiles && (on_x || on_y)))
-        return fail(nullptr, LBM_EDEVICE, "tile in the wrong set");
+      const int touched = (tmp.geo.wall_x && x0 == 0 ? 1 : 0) | (tmp.geo.wall_x && x0 + tx > tmp.geo.nx - 2 ? 2 : 0) |
+                          (tmp.geo.wall_y && y0 == 0 ? 4 : 0) | (tmp.geo.wall_y && y0 + ty > tmp.geo.ny - 2 ? 8 : 0);
+      if (walls && (touched & ~lat_mode_of(set, true)) != 0) return fail(nullptr, LBM_EDEVICE, "tile in the wrong set");
       counts[b * nt + j * s.tiles_x + i]++;
     }
   }

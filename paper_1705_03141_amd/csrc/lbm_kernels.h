@@ -43,33 +43,79 @@ struct StepArgs {
 
 // The tiles one launch of the step kernel covers.  With lateral walls the tiles whose cells
 // and ring cells are all off the walls (the interior rectangle) take the plain pull.  The
-// frame around it is split by the walls its tiles touch: the x edges (tiles left and right
-// of the rectangle, in its rows), the y edges (above and below it, in its columns) and the
-// corners; each takes the instance that reflects at those walls only.
-enum TileSet { kAllTiles = 0, kInteriorTiles = 1, kFrameX = 2, kFrameY = 3, kCorners = 4 };
+// frame around it is split by the walls its tiles touch: left and right of the rectangle (in
+// its rows) the tiles touch only x walls, -x on the left and +x on the right; below and above
+// it (in its columns) only y walls; the corner blocks touch both axes.  The edges are one set
+// per axis (kEdgeX, kEdgeY) or one per wall (kEdgeXLo ... kEdgeYHi); each set takes the
+// instance that reflects at its walls only.
+enum TileSet {
+  kAllTiles = 0,
+  kInteriorTiles = 1,
+  kEdgeX = 2,
+  kEdgeY = 3,
+  kEdgeXLo = 4,
+  kEdgeXHi = 5,
+  kEdgeYLo = 6,
+  kEdgeYHi = 7,
+  kCorners = 8
+};
 
-// Reflection mode of the step kernel instance for a tile set: bit 0 x walls, bit 1 y walls.
+// The tile sets a step of a lattice with lateral walls launches, by storage code (0 FP32, 1
+// FP16, 2 BF16): with FP16 storage one set per wall along the edges, because its instances
+// that reflect at both walls of an axis spill registers (measured on the jet between walls:
+// 4.82 against 5.99 ms per step); with the others one per axis, where the extra launches of
+// the per-wall split cost more than it saves.  Returns the count written to sets.
+inline int wall_tile_sets(int storage, int* sets) {
+  int n = 0;
+  sets[n++] = kInteriorTiles;
+  if (storage == 1) {
+    sets[n++] = kEdgeXLo;
+    sets[n++] = kEdgeXHi;
+    sets[n++] = kEdgeYLo;
+    sets[n++] = kEdgeYHi;
+  } else {
+    sets[n++] = kEdgeX;
+    sets[n++] = kEdgeY;
+  }
+  sets[n++] = kCorners;
+  return n;
+}
+
+// Reflection mode of the step kernel instance for a tile set: the walls it reflects at, in
+// the bits of wall_flags (1: -x, 2: +x, 4: -y, 8: +y).
 __host__ __device__ inline int lat_mode_of(int tile_set, bool walls) {
   if (!walls || tile_set == kInteriorTiles) return 0;
-  return tile_set == kFrameX ? 1 : (tile_set == kFrameY ? 2 : 3);
+  switch (tile_set) {
+    case kEdgeX: return 3;
+    case kEdgeY: return 12;
+    case kEdgeXLo: return 1;
+    case kEdgeXHi: return 2;
+    case kEdgeYLo: return 4;
+    case kEdgeYHi: return 8;
+    default: return 15;
+  }
 }
 
 __host__ __device__ inline int tiles_in_set(const StepArgs& a) {
   const int w_in = a.tx_hi - a.tx_lo, h_in = a.ty_hi - a.ty_lo;
-  const int side = a.tx_lo + (a.tiles_x - a.tx_hi), rows_out = a.ty_lo + (a.tiles_y - a.ty_hi);
+  const int x_hi = a.tiles_x - a.tx_hi, y_hi = a.tiles_y - a.ty_hi;
   switch (a.tile_set) {
     case kInteriorTiles: return w_in * h_in;
-    case kFrameX: return side * h_in;
-    case kFrameY: return w_in * rows_out;
-    case kCorners: return side * rows_out;
+    case kEdgeX: return (a.tx_lo + x_hi) * h_in;
+    case kEdgeY: return w_in * (a.ty_lo + y_hi);
+    case kEdgeXLo: return a.tx_lo * h_in;
+    case kEdgeXHi: return x_hi * h_in;
+    case kEdgeYLo: return w_in * a.ty_lo;
+    case kEdgeYHi: return w_in * y_hi;
+    case kCorners: return (a.tx_lo + x_hi) * (a.ty_lo + y_hi);
     default: return a.tiles_x * a.tiles_y;
   }
 }
 
 // Tile (txi, tyi) of the t-th tile of the launch's set (row by row within the set).
 __host__ __device__ inline void tile_of(const StepArgs& a, int t, int& txi, int& tyi) {
-  const int w_in = a.tx_hi - a.tx_lo, side = a.tx_lo + (a.tiles_x - a.tx_hi);
-  // the k-th column index left or right of the rectangle, and the r-th row above or below it
+  const int w_in = a.tx_hi - a.tx_lo, x_hi = a.tiles_x - a.tx_hi, side = a.tx_lo + x_hi;
+  // the k-th column left or right of the rectangle, and the r-th row below or above it
   auto side_col = [&](int k) { return k < a.tx_lo ? k : a.tx_hi + (k - a.tx_lo); };
   auto out_row = [&](int r) { return r < a.ty_lo ? r : a.ty_hi + (r - a.ty_lo); };
   switch (a.tile_set) {
@@ -77,12 +123,28 @@ __host__ __device__ inline void tile_of(const StepArgs& a, int t, int& txi, int&
       tyi = a.ty_lo + t / w_in;
       txi = a.tx_lo + t % w_in;
       return;
-    case kFrameX:
+    case kEdgeX:
       tyi = a.ty_lo + t / side;
       txi = side_col(t % side);
       return;
-    case kFrameY:
+    case kEdgeY:
       tyi = out_row(t / w_in);
+      txi = a.tx_lo + t % w_in;
+      return;
+    case kEdgeXLo:
+      tyi = a.ty_lo + t / a.tx_lo;
+      txi = t % a.tx_lo;
+      return;
+    case kEdgeXHi:
+      tyi = a.ty_lo + t / x_hi;
+      txi = a.tx_hi + t % x_hi;
+      return;
+    case kEdgeYLo:
+      tyi = t / w_in;
+      txi = a.tx_lo + t % w_in;
+      return;
+    case kEdgeYHi:
+      tyi = a.ty_hi + t / w_in;
       txi = a.tx_lo + t % w_in;
       return;
     case kCorners:

@@ -116,21 +116,27 @@ __device__ __forceinline__ void column_offsets(const Geo& G, int x, int y, unsig
     for (int a = 0; a < 3; ++a) o[b][a] = (unsigned)((ys[b] * G.nx + xs[a]) * (int)sizeof(T));
 }
 
-// Lateral reflection of a source offset at a cell with wall flags wf (wall_flags): true where
-// the source (dx, dy) lies beyond a free-slip wall in x (AXIS 0) or y (AXIS 1).  LAT is the
-// instance's reflection mode (bit 0: x walls, bit 1: y walls); an axis it leaves out never
-// reflects.
-template <int AXIS, int D, int LAT>
-__device__ __forceinline__ bool reflects(int wf) {
-  if constexpr (D == 0 || (LAT & (1 << AXIS)) == 0) return false;
-  constexpr int bit = (AXIS == 0 ? 0 : 2) + (D < 0 ? 0 : 1);
-  return (wf >> bit) & 1;
+// Bit of wall_flags for the wall a source offset D along AXIS (0: x, 1: y) crosses.
+template <int AXIS, int D>
+constexpr int wall_bit() {
+  return (AXIS == 0 ? 0 : 2) + (D < 0 ? 0 : 1);
 }
 
-// Whether direction i of a pull can reflect at a lateral wall in reflection mode LAT.
+// Lateral reflection of a source offset at a cell with wall flags wf (wall_flags): true where
+// the source (dx, dy) lies beyond a free-slip wall in x (AXIS 0) or y (AXIS 1).  LAT is the
+// instance's reflection mode, the walls it reflects at in the bits of wall_flags; a wall it
+// leaves out never reflects.
+template <int AXIS, int D, int LAT>
+__device__ __forceinline__ bool reflects(int wf) {
+  if constexpr (D == 0 || ((LAT >> wall_bit<AXIS, D>()) & 1) == 0) return false;
+  else return (wf >> wall_bit<AXIS, D>()) & 1;
+}
+
+// Whether a pull direction with source offset (DX, DY) can reflect at a lateral wall in
+// reflection mode LAT.
 template <int LAT, int DX, int DY>
 constexpr bool lat_dir() {
-  return ((LAT & 1) && DX != 0) || ((LAT & 2) && DY != 0);
+  return (DX != 0 && ((LAT >> wall_bit<0, DX>()) & 1)) || (DY != 0 && ((LAT >> wall_bit<1, DY>()) & 1));
 }
 
 // Issue the 27 population loads of a pull in mode MODE.  slab[k] covers the 27 population
@@ -325,10 +331,10 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   // Issue order of a pass's loads (measured): with FP32 populations the staged scalars go
   // first, with 16-bit populations after the population loads.  Their LDS write waits until
   // the pull is complete, so that the pull consumes each population load as soon as it and
-  // the older loads have arrived, rather than after all of them.  The corner instance (x and
-  // y walls), which spills, keeps the scalars first and their LDS write before the pull.
-  constexpr bool kStoreLate = LAT != 3;
-  constexpr bool kStageFirst = LAT == 3 || sizeof(T) == 4;
+  // the older loads have arrived, rather than after all of them.  The corner instance (all
+  // walls), which spills, keeps the scalars first and their LDS write before the pull.
+  constexpr bool kStoreLate = LAT != 15;
+  constexpr bool kStageFirst = LAT == 15 || sizeof(T) == 4;
 
   const Geo& G = A.geo;
   const bool zper = G.face_lo == FACE_PERIODIC;
@@ -370,7 +376,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   const int sR = (ry + 2) * SX + rx + 2, dR = (ry + 1) * DX + rx + 1;
   // lateral wall flags of the own and the ring cell (0 without lateral walls)
   // (only the walls of the instance's mode: the tiles it serves touch no others)
-  constexpr int kWallMask = ((LAT & 1) ? 3 : 0) | ((LAT & 2) ? 12 : 0);
+  constexpr int kWallMask = LAT;
   const int wfI = LAT ? wall_flags(G, gx, gy) & kWallMask : 0, wfR = LAT ? wall_flags(G, rgx, rgy) & kWallMask : 0;
   // staged cells
   unsigned stOff[KS];  // byte offsets in a scalar plane
@@ -666,17 +672,34 @@ hipError_t launch_step_lat(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The step kernel with lateral free-slip walls comes in instances that reflect at x walls, y
-// walls or both, each for the frame tiles that touch those walls; lattices with periodic
-// sides, and the interior tiles of a lattice with walls, keep the plain pull.
+// Whether storage type T takes one step-kernel instance per lateral wall along the frame's
+// edges (FP16 storage) rather than one per axis (wall_tile_sets on the host side).
+template <typename T>
+constexpr bool kWallPerSide = std::is_same<T, _Float16>::value;
+
+// The step kernel with lateral free-slip walls comes in instances that reflect at the walls
+// of one axis or one wall (the frame's edges, by storage) or at all four (its corners);
+// lattices with periodic sides, and the interior tiles of a lattice with walls, keep the
+// plain pull.  Only the modes of T's tile sets are instantiated.
 template <typename T, int TX, int TY>
 hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
-  switch (lat_mode_of(a.tile_set, a.geo.wall_x || a.geo.wall_y)) {
-    case 1: return launch_step_lat<T, TX, TY, 1>(a, s);
-    case 2: return launch_step_lat<T, TX, TY, 2>(a, s);
-    case 3: return launch_step_lat<T, TX, TY, 3>(a, s);
-    default: return launch_step_lat<T, TX, TY, 0>(a, s);
+  const int mode = lat_mode_of(a.tile_set, a.geo.wall_x || a.geo.wall_y);
+  if (mode == 0) return launch_step_lat<T, TX, TY, 0>(a, s);
+  if (mode == 15) return launch_step_lat<T, TX, TY, 15>(a, s);
+  if constexpr (kWallPerSide<T>) {
+    switch (mode) {
+      case 1: return launch_step_lat<T, TX, TY, 1>(a, s);
+      case 2: return launch_step_lat<T, TX, TY, 2>(a, s);
+      case 4: return launch_step_lat<T, TX, TY, 4>(a, s);
+      case 8: return launch_step_lat<T, TX, TY, 8>(a, s);
+    }
+  } else {
+    switch (mode) {
+      case 3: return launch_step_lat<T, TX, TY, 3>(a, s);
+      case 12: return launch_step_lat<T, TX, TY, 12>(a, s);
+    }
   }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int TX, int TY, int LAT>
@@ -694,12 +717,22 @@ hipError_t launch_batch_lat(const StepArgs* cases, const int* first, int ncases,
 template <typename T, int TX, int TY>
 hipError_t launch_batch_tile(const StepArgs* cases, const int* first, int ncases, int nblocks, bool init, int lat,
                              hipStream_t s) {
-  switch (lat) {
-    case 1: return launch_batch_lat<T, TX, TY, 1>(cases, first, ncases, nblocks, init, s);
-    case 2: return launch_batch_lat<T, TX, TY, 2>(cases, first, ncases, nblocks, init, s);
-    case 3: return launch_batch_lat<T, TX, TY, 3>(cases, first, ncases, nblocks, init, s);
-    default: return launch_batch_lat<T, TX, TY, 0>(cases, first, ncases, nblocks, init, s);
+  if (lat == 0) return launch_batch_lat<T, TX, TY, 0>(cases, first, ncases, nblocks, init, s);
+  if (lat == 15) return launch_batch_lat<T, TX, TY, 15>(cases, first, ncases, nblocks, init, s);
+  if constexpr (kWallPerSide<T>) {
+    switch (lat) {
+      case 1: return launch_batch_lat<T, TX, TY, 1>(cases, first, ncases, nblocks, init, s);
+      case 2: return launch_batch_lat<T, TX, TY, 2>(cases, first, ncases, nblocks, init, s);
+      case 4: return launch_batch_lat<T, TX, TY, 4>(cases, first, ncases, nblocks, init, s);
+      case 8: return launch_batch_lat<T, TX, TY, 8>(cases, first, ncases, nblocks, init, s);
+    }
+  } else {
+    switch (lat) {
+      case 3: return launch_batch_lat<T, TX, TY, 3>(cases, first, ncases, nblocks, init, s);
+      case 12: return launch_batch_lat<T, TX, TY, 12>(cases, first, ncases, nblocks, init, s);
+    }
   }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>

@@ -426,10 +426,11 @@ def selftest_collide_host(problem, fr, fb, grad_phi, grad_rho):
     return outr, outb
 
 
-def selftest_tile_sets_host(problem, tx: int, ty: int) -> np.ndarray:
+def selftest_tile_sets_host(problem, tx: int, ty: int, storage: str = "f32") -> np.ndarray:
     """How the step's launches cover the tiles of tx x ty (diagnostic; no GPU): counts of shape
-    (3, tiles_y, tiles_x) for the launch over all tiles, the interior tiles and the frame."""
-    p = params_from_problem(problem)
+    (3, tiles_y, tiles_x) for the launch over all tiles, the interior tiles and the frame (whose
+    split into launches depends on the storage type)."""
+    p = params_from_problem(problem, storage)
     ntx, nty = -(-problem.nx // tx), -(-problem.ny // ty)
     counts = np.zeros(3 * ntx * nty, dtype=np.int32)
     st = library().lbm_selftest_tile_sets_host(ctypes.byref(p), int(tx), int(ty),

@@ -385,6 +385,15 @@ def cfg_jet(steps: int = 30000) -> Problem:
     return pb
 
 
+def cfg_jet_walls(steps: int = 30000) -> Problem:
+    """The jet of ``cfg_jet`` between free-slip lateral walls, as in the paper's own jet runs
+    (Sec. IV A)."""
+    pb = jet(nx=256, ny=256, nz=1024, diameter=16.0, u_in=0.04, gamma=1.6, nu_c=1.8e-4, eta=1.0, weber=220.0,
+             froude=8.5, noise_rel=0.01, seed=3, steps=steps, lateral=FREESLIP)
+    pb.name = "jet_walls_256x256x1024"
+    return pb
+
+
 def small_configs():
     """Parity-sized problems: the 32^3 static droplet, a droplet with Suga's rates at a
     viscosity where they are stable, a reduced Rayleigh-Taylor box and a reduced jet with

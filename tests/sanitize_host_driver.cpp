@@ -97,13 +97,15 @@ int main() {
     }
   EXPECT(lbm_selftest_collide_host(nullptr, fr, fb, grads[0], grads[0], outr, outb) == LBM_EINVAL);
 
-  // tile cover of the step's launches, with and without lateral walls: every tile once
+  // tile cover of the step's launches, with and without lateral walls, for the per-axis and
+  // the per-wall (FP16) split of the frame: every tile once
   const int shapes[5][2] = {{32, 4}, {32, 8}, {64, 4}, {64, 8}, {32, 16}};
-  for (int walls = 0; walls < 2; ++walls)
+  for (int walls = 0; walls < 4; ++walls)
     for (const auto& sh : shapes) {
       lbm_params q = base();
       q.nx = 200; q.ny = 72;
-      if (walls) q.face[0] = q.face[1] = q.face[2] = q.face[3] = LBM_FREESLIP;
+      q.storage = (walls & 2) ? LBM_F32 : LBM_F16;
+      if (walls & 1) q.face[0] = q.face[1] = q.face[2] = q.face[3] = LBM_FREESLIP;
       const int tx = (q.nx + sh[0] - 1) / sh[0], ty = (q.ny + sh[1] - 1) / sh[1], nt = tx * ty;
       int counts[3 * 7 * 18];
       EXPECT(3 * nt <= (int)(sizeof(counts) / sizeof(int)));

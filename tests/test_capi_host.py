@@ -7,6 +7,7 @@
   per-colour post-collision populations.
 """
 import ctypes
+import itertools
 
 import numpy as np
 import pytest
@@ -156,15 +157,16 @@ def test_sigma_helpers_match_table2(L):
                                         ((96, 64, 8), "y"), ((70, 36, 20), ""), ((37, 29, 23), "xy")])
 def test_tile_sets_cover_every_tile_once(L, dims, faces):
     """With lateral walls the step launches the plain pull over the interior tiles and the
-    reflecting instance over the frame: every tile is processed exactly once, and a tile is
-    interior exactly when none of its cells or ring cells lies on a wall (checked here from
-    the geometry, cell by cell)."""
+    reflecting instances over the frame (one launch per axis, or per wall with FP16 storage):
+    every tile is processed exactly once, a tile is interior exactly when none of its cells or
+    ring cells lies on a wall (checked here from the geometry, cell by cell), and no frame tile
+    touches a wall its launch does not reflect at (checked by the library)."""
     pb = W.static_droplet(dims=dims, radius=3.0, rho_r0=1.5, rho_b0=1.0, nu=0.05, A=0.01)
     pb.faces = (W.FREESLIP if "x" in faces else W.PERIODIC,) * 2 + (W.FREESLIP if "y" in faces else W.PERIODIC,) * 2 \
         + (W.FREESLIP, W.FREESLIP)
     nx, ny = dims[0], dims[1]
-    for tx, ty in ((32, 4), (32, 8), (64, 4), (64, 8), (32, 16)):
-        c = lbm.selftest_tile_sets_host(pb, tx, ty)
+    for (tx, ty), storage in itertools.product(((32, 4), (32, 8), (64, 4), (64, 8), (32, 16)), ("f32", "f16")):
+        c = lbm.selftest_tile_sets_host(pb, tx, ty, storage)
         assert np.all(c.sum(axis=0) == 1), (tx, ty)
         if not faces:
             assert np.all(c[0] == 1)
