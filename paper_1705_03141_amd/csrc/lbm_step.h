@@ -331,10 +331,13 @@ __device__ __forceinline__ void step_body(const StepArgs& A, int L, const int nb
   // Issue order of a pass's loads (measured): with FP32 populations the staged scalars go
   // first, with 16-bit populations after the population loads.  Their LDS write waits until
   // the pull is complete, so that the pull consumes each population load as soon as it and
-  // the older loads have arrived, rather than after all of them.  The corner instance (all
-  // walls), which spills, keeps the scalars first and their LDS write before the pull.
-  constexpr bool kStoreLate = LAT != 15;
-  constexpr bool kStageFirst = LAT == 15 || sizeof(T) == 4;
+  // the older loads have arrived, rather than after all of them.  The instances that spill
+  // (the corner instance, and with FP16 storage every reflecting one) keep the scalars first
+  // and their LDS write before the pull, so that the staged values are not live across it
+  // (FP16 jet between walls: 4.47 against 4.81 ms per step).
+  constexpr bool kHalfWall = std::is_same<T, _Float16>::value && LAT != 0;
+  constexpr bool kStoreLate = LAT != 15 && !kHalfWall;
+  constexpr bool kStageFirst = LAT == 15 || sizeof(T) == 4 || kHalfWall;
 
   const Geo& G = A.geo;
   const bool zper = G.face_lo == FACE_PERIODIC;
