@@ -42,22 +42,23 @@ def test_batch_matches_single_lattices():
     b.close()
 
 
-def test_batch_with_lateral_walls_matches_single_lattices():
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_with_lateral_walls_matches_single_lattices(storage):
     """Cases with free-slip lateral walls next to periodic ones: a wall case runs its interior
-    tiles in a plain group and its frame in a reflecting group of the batch, and still ends
-    bitwise equal to its single-lattice run."""
+    tiles in a plain group and its frame in reflecting groups of the batch (one per axis, or
+    one per wall with FP16 storage), and still ends bitwise equal to its single-lattice run."""
     cases = small_sweep(3)
     walls = [W.jet(nx=200, ny=72, nz=64, diameter=10.0, seed=5, lateral=W.FREESLIP),
              W.jet(nx=40, ny=40, nz=48, diameter=6.0, seed=6, lateral=W.FREESLIP)]
     cases = cases + walls
-    log("[batch, walls] " + ", ".join(f"{c.nx}x{c.ny}x{c.nz}" for c in cases))
-    b = lbm.Batch(cases)
+    log(f"[batch, walls, {storage}] " + ", ".join(f"{c.nx}x{c.ny}x{c.nz}" for c in cases))
+    b = lbm.Batch(cases, storage=storage)
     b.step(30)
     b.sync()
     tx, ty, _ = b.cases[len(cases) - 2].tiling()
-    assert lbm.selftest_tile_sets_host(walls[0], tx, ty)[1].sum() > 0, "no interior tiles in the wall case"
+    assert lbm.selftest_tile_sets_host(walls[0], tx, ty, storage)[1].sum() > 0, "no interior tiles in the wall case"
     for k, pb in enumerate(cases):
-        alone = lbm.Lattice(pb, tiling=b.cases[k].tiling())
+        alone = lbm.Lattice(pb, storage=storage, tiling=b.cases[k].tiling())
         alone.step(30)
         same = bool(np.array_equal(b.cases[k].populations(), alone.populations()))
         alone.close()
